@@ -1,0 +1,102 @@
+"""Oracle pins: reunitarisation, the disordered (Haar) start, SU(3)
+membership after sweeps, gauge invariance (plaquette and staple)."""
+import numpy as np
+import pytest
+
+from paper_0904_0642_amd import workloads
+
+
+def _defects(links):
+    u = links.reshape(-1, 3, 3)
+    uu = np.einsum("nij,nkj->nik", u, u.conj())
+    unit = np.abs(uu - np.eye(3)).max()
+    det = np.abs(np.linalg.det(u) - 1).max()
+    return unit, det
+
+
+def test_reunitarize_projects_to_su3(oracle_mod):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        m = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+        r = oracle_mod.reunitarize(m)
+        assert np.abs(r @ r.conj().T - np.eye(3)).max() < 1e-14
+        assert abs(np.linalg.det(r) - 1) < 1e-14
+        # Gram-Schmidt keeps the direction of row 0 and the span of rows 0,1
+        assert np.allclose(r[0], m[0] / np.linalg.norm(m[0]), atol=1e-14)
+        assert np.allclose(r[2], np.conj(np.cross(r[0], r[1])), atol=1e-14)
+    g = workloads.random_su3(rng, 20)
+    for u in g:
+        assert np.abs(oracle_mod.reunitarize(u) - u).max() < 1e-14
+
+
+def test_hot_start_is_haar(oracle_mod):
+    # E Tr U = 0, E |Tr U|^2 = 1, E (Tr U)^3 = 1 (the last one is specific to
+    # SU(3): it vanishes for U(3), so it checks det U = 1).
+    L = oracle_mod.Lattice([16, 16, 16, 16], seed=1)
+    L.hot_start()
+    u = L.get_links().reshape(-1, 3, 3)
+    unit, det = _defects(u)
+    assert unit < 1e-13 and det < 1e-13
+    tr = np.trace(u, axis1=1, axis2=2)
+    n = len(tr)
+    assert abs(tr.mean()) < 5 / np.sqrt(n)
+    assert abs(np.mean(np.abs(tr) ** 2) - 1) < 5 / np.sqrt(n)
+    m3 = np.mean(tr ** 3)
+    assert abs(m3 - 1) < 5 * np.sqrt(6 / n)
+    # the start depends on the seed, and not on anything else
+    L2 = oracle_mod.Lattice([16, 16, 16, 16], seed=1)
+    L2.hot_start()
+    assert np.array_equal(L2.get_links(), L.get_links())
+    L3 = oracle_mod.Lattice([16, 16, 16, 16], seed=2)
+    L3.hot_start()
+    assert not np.array_equal(L3.get_links(), L.get_links())
+
+
+@pytest.mark.parametrize("ext,nlat,mask", [([4, 4, 4, 4], 1, 0), ([4, 2, 4], 1, 0), ([4, 4, 2, 2], 2, 0b1111)])
+def test_links_stay_in_su3(oracle_mod, ext, nlat, mask):
+    L = oracle_mod.Lattice(ext, nlat=nlat, dlt_mask=mask, seed=5)
+    L.hot_start()
+    for _ in range(4):
+        L.sweep(5.7, nhit=8, nsweeps=1)
+        unit, det = _defects(L.get_links())
+        assert unit < 1e-12 and det < 1e-12
+
+
+def _gauge_transform(L, links, g):
+    """U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag using the oracle's neighbour map."""
+    out = links.copy()
+    for layer in range(L.nlat):
+        for s in range(L.V):
+            for mu in range(L.nd):
+                lo, so = L.neighbor(layer, s, mu, +1)
+                out[layer, s, mu] = g[layer, s] @ links[layer, s, mu] @ g[lo, so].conj().T
+    return out
+
+
+@pytest.mark.parametrize("ext,nlat,mask", [([4, 4, 4, 4], 1, 0), ([4, 4, 2], 2, 0b111), ([4, 2, 4, 2], 2, 0b0111)])
+def test_gauge_invariance(oracle_mod, ext, nlat, mask):
+    rng = np.random.default_rng(11)
+    L = oracle_mod.Lattice(ext, nlat=nlat, dlt_mask=mask, seed=9)
+    L.hot_start()
+    L.sweep(5.5, 6.0, nhit=4, nsweeps=2)
+    links = L.get_links()
+    p0 = L.plaquette(5.5, 6.0)
+    ra0 = []
+    for layer in range(nlat):
+        for s in (0, 3, L.V - 1):
+            for mu in range(L.nd):
+                a = L.staple(layer, s, mu, 5.5, 6.0)
+                ra0.append(np.trace(links[layer, s, mu] @ a).real)
+    g = workloads.random_su3(rng, nlat * L.V).reshape(nlat, L.V, 3, 3)
+    L.set_links(_gauge_transform(L, links, g))
+    p1 = L.plaquette(5.5, 6.0)
+    good = ~np.isnan(p0)
+    assert np.allclose(p0[good], p1[good], rtol=1e-13, atol=1e-13)
+    links1 = L.get_links()
+    ra1 = []
+    for layer in range(nlat):
+        for s in (0, 3, L.V - 1):
+            for mu in range(L.nd):
+                a = L.staple(layer, s, mu, 5.5, 6.0)
+                ra1.append(np.trace(links1[layer, s, mu] @ a).real)
+    assert np.allclose(ra0, ra1, rtol=0, atol=1e-12)
