@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: checkerboard Cabibbo-Marinari / FHKP SU(3) heatbath sweeps on one MI355X.
+
+A step is one sweep of the whole hot path -- 2D checkerboard slice updates
+(staple, three SU(2) subgroup heatbaths in multi-hit form, reunitarisation,
+fused action bookkeeping) followed by the plaquette measurement -- on a
+resident lattice.  Default workload: D = 4, 48^4 periodic torus, beta = 6.2,
+FP64 links (18 reals), disordered (Haar) start from seed 1, n_hit = 8; the
+FP32 12-real form is run beside it on a 64^4 lattice of about the same size
+in HBM.  Inputs are synthetic (the start is drawn from the Philox stream).
+
+Prints one JSON line.  `value` is link updates per second over the timed
+sweeps; `roofline` prices the slice-update kernel against 8 TB/s with the
+algorithmic bytes per launch (2D+1) * bytes_per_link * V/2 (one read of every
+link of the lattice, one write of the updated half-direction), divided by the
+kernel's average duration measured with HIP events around each launch.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_0642_amd", "csrc", f)
+                  for f in ("update.hip", "device_math.h", "geometry.h", "layout.h")]
+
+WORKLOADS = {
+    # name: (extents, precision, beta)
+    "48^4-fp64": ((48, 48, 48, 48), 0, 6.2),
+    "64^4-fp32-12": ((64, 64, 64, 64), 2, 6.2),
+    "64^4-fp32-18": ((64, 64, 64, 64), 1, 6.2),
+    "16^4-fp64": ((16, 16, 16, 16), 0, 6.0),
+}
+PREC_NAME = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12"}
+PREC_DTYPE = {0: "f64", 1: "f32 links + f64 heatbath", 2: "f32 (12-real) links + f64 heatbath"}
+BYTES_PER_LINK = {0: 144, 1: 72, 2: 48}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, algorithmic_bytes: float):
+    """HBM bytes per update launch from the committed rocprofv3 counter runs,
+    or None when absent or taken on different kernel sources."""
+    path = os.path.join(PROFILES, f"update_kernel_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int):
+    import torch
+
+    import paper_0904_0642_amd as su3hb
+
+    ext, prec, beta = WORKLOADS[name]
+    D = len(ext)
+    V = int(np.prod(ext))
+    lat = su3hb.Lattice(ext, precision=prec, start=su3hb.HOT, seed=1)
+    if autotune_ms > 0:
+        lat.autotune(autotune_ms)
+    block, xcd = lat.get_launch()
+    if warmup > 0:
+        lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timing, series = lat.sweep_timed(beta, n_hit=n_hit, n_sweeps=steps, measure=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    links_per_sweep = V * D
+    rate = steps * links_per_sweep / secs
+    upd_ms = timing[0] / max(timing[1], 1)
+    plq_ms = timing[2] / max(timing[3], 1)
+    S = BYTES_PER_LINK[prec]
+    bytes_per_launch = (2 * D + 1) * S * (V // 2)
+    achieved = bytes_per_launch / (upd_ms * 1e-3) / 1e9
+    traffic = measured_traffic(name, bytes_per_launch)
+    plaq = series[:, 0]
+    out = {
+        "rate": rate, "secs": secs, "ms_per_step": 1e3 * secs / steps,
+        "update_kernel_ms": upd_ms, "plaquette_kernel_ms": plq_ms,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "kernel": f"update_kernel<{D},{PREC_NAME[prec]}>"},
+        "plaquette_first_last": [float(plaq[0]), float(plaq[-1])],
+        "launch": {"block": block, "xcd_remap": xcd},
+        "extents": list(ext), "precision": PREC_NAME[prec], "beta": beta, "links_per_sweep": links_per_sweep,
+    }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(name: str, n_hit: int):
+    """The FP64 oracle on a bounded sample of the same workload: the first two
+    checkerboard slices (parity 0, directions 0 and 1) of the hot-started
+    lattice, with OpenMP over the sites of a slice on the host cores."""
+    import oracle
+
+    ext, prec, beta = WORKLOADS[name]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Lattice(list(ext), seed=1, threads=threads)
+    o.hot_start()
+    V = int(np.prod(ext))
+    t0 = time.perf_counter()
+    for mu in (0, 1):
+        o.update_slice(0, mu, beta, beta, nhit=n_hit)
+    secs = time.perf_counter() - t0
+    n = 2 * (V // 2)
+    return {"value": n / secs, "unit": "link updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"2 checkerboard slices ({n} link updates) of the hot-started {'x'.join(map(str, ext))} "
+                      f"lattice at beta={beta}, n_hit={n_hit}, FP64 C oracle, OpenMP {threads} threads, "
+                      f"{secs:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="48^4-fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--compare", default="64^4-fp32-12", help="second leg ('' to skip)")
+    ap.add_argument("--n-hit", type=int, default=8)
+    ap.add_argument("--autotune-ms", type=int, default=400)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (for scaling HBM counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the whole lattice is resident on a single MI355X; "
+              "multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_0904_0642_amd as su3hb
+    su3hb.lib()
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+
+    main_leg = run_leg(args.workload, args.steps, args.warmup, args.n_hit, args.autotune_ms)
+    legs = {}
+    if args.compare and args.compare != args.workload:
+        legs[args.compare] = run_leg(args.compare, args.steps, args.warmup, args.n_hit, args.autotune_ms)
+
+    ext, prec, beta = WORKLOADS[args.workload]
+    line = {
+        "metric": "SU(3) link updates/sec + % HBM roofline, FP32 vs FP64 at equal <P> error",
+        "value": round(main_leg["rate"], 1),
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_leg["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": PREC_DTYPE[prec],
+        "data": "synthetic (Haar start from the seeded Philox stream)",
+        "config": {"workload": f"checkerboard CM/FHKP heatbath, D=4 {'x'.join(map(str, ext))} periodic torus, "
+                               f"beta={beta}, {PREC_NAME[prec]} links, hot start seed 1, n_hit={args.n_hit}, "
+                               f"plaquette every sweep",
+                   "lattice": list(ext), "precision": PREC_NAME[prec], "beta": beta, "n_hit": args.n_hit,
+                   "links_per_sweep": main_leg["links_per_sweep"], "launch": main_leg["launch"]},
+        "roofline": main_leg["roofline"],
+        "update_kernel_ms": round(main_leg["update_kernel_ms"], 5),
+        "plaquette_kernel_ms": round(main_leg["plaquette_kernel_ms"], 5),
+        "plaquette_first_last": main_leg["plaquette_first_last"],
+    }
+    for name, leg in legs.items():
+        line["compare_" + name] = {
+            "value": round(leg["rate"], 1), "unit": "link updates/s", "ms_per_step": round(leg["ms_per_step"], 4),
+            "roofline": leg["roofline"], "update_kernel_ms": round(leg["update_kernel_ms"], 5),
+            "plaquette_kernel_ms": round(leg["plaquette_kernel_ms"], 5), "launch": leg["launch"],
+            "plaquette_first_last": leg["plaquette_first_last"],
+            "rate_ratio_vs_main": round(leg["rate"] / main_leg["rate"], 3),
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.n_hit)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,8 @@ def lib():
         L.or_update_slice.restype = C.c_double
         L.or_sweep.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, dp]
         L.or_plaquette.argtypes = [C.c_void_p, C.c_double, C.c_double, dp]
+        L.or_get_link.argtypes = [C.c_void_p, C.c_int, C.c_long, C.c_int, dp]
+        L.or_put_link.argtypes = [C.c_void_p, C.c_int, C.c_long, C.c_int, dp]
         _lib = L
     return _lib
 
@@ -185,6 +187,15 @@ class Lattice:
         a = np.ascontiguousarray(np.asarray(links, dtype=np.complex128)).view(np.float64).reshape(-1)
         if lib().or_set_links(self._h, _dptr(a), a.size) != 0:
             raise ValueError("set_links size mismatch")
+
+    def get_link(self, layer, s, mu) -> np.ndarray:
+        out = np.zeros(18)
+        lib().or_get_link(self._h, int(layer), int(s), int(mu), _dptr(out))
+        return out.view(np.complex128).reshape(3, 3)
+
+    def put_link(self, layer, s, mu, u):
+        a = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(3, 3)).view(np.float64).reshape(-1)
+        lib().or_put_link(self._h, int(layer), int(s), int(mu), _dptr(np.ascontiguousarray(a)))
 
     def site_index(self, x) -> int:
         xx = (C.c_int * _MAXD)(*[int(v) for v in x])

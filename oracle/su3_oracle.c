@@ -418,6 +418,9 @@ void or_hot_start(void *h)
 {
     olat *L = (olat *)h;
     for (int layer = 0; layer < L->nlat; ++layer)
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(L->nthreads)
+#endif
         for (long s = 0; s < L->V; ++s)
             for (int mu = 0; mu < L->nd; ++mu) {
                 uint32_t lid = link_id(L, layer, s, mu);
@@ -579,4 +582,15 @@ void or_plaquette(void *h, double beta0, double beta1, double out[6])
     out[3] = lay[0] / ((double)L->V * D * (D - 1) / 2.0);
     out[4] = L->nlat == 2 ? lay[1] / ((double)L->V * D * (D - 1) / 2.0) : NAN;
     out[5] = weighted;
+}
+
+/* Test hook: read or write one link (18 doubles) without copying the lattice. */
+void or_get_link(void *h, int layer, long s, int mu, double *out18)
+{
+    memcpy(out18, link_at((const olat *)h, layer, s, mu), sizeof(su3));
+}
+
+void or_put_link(void *h, int layer, long s, int mu, const double *in18)
+{
+    memcpy(link_at((const olat *)h, layer, s, mu), in18, sizeof(su3));
 }

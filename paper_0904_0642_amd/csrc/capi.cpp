@@ -1,0 +1,917 @@
+// capi.cpp -- the extern "C" boundary of libsu3hb.so (declared in
+// include/su3hb.h): argument checks, device memory, the sweep driver
+// (parity outer, direction inner; one launch per slice, replayed from a
+// captured HIP graph), measurement, canonical get/set, autotuning and batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/su3hb.h"
+#include "kernels.h"
+#include "layout.h"
+
+using namespace su3hb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(SU3HB_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                 \
+    } while (0)
+
+constexpr int kPlaqBlock = 256;
+constexpr uint32_t kSeriesCap = 4096;
+constexpr size_t kStageBytes = size_t(256) << 20;
+
+struct GraphCache {
+    bool valid = false;
+    double b0 = 0, b1 = 0;
+    int nhit = 0, measure = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct su3hb_lattice {
+    int device = 0;
+    int nd = 0, prec = 0, nrep = 0;
+    bool batch = false;
+    std::vector<RepDesc> reps;
+    RepDesc *d_reps = nullptr;
+    void *links = nullptr;
+    size_t links_bytes = 0;
+    bool owns_links = false;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    uint32_t *d_sweep = nullptr;
+    uint64_t sweep = 0;
+    uint64_t seed = 0;
+    StatSlot *d_stats = nullptr;
+    StatSlot *d_stats_out = nullptr;
+    double *d_partials = nullptr;
+    double *d_plaq = nullptr;
+    double *d_series = nullptr;
+    uint32_t *d_cursor = nullptr;
+    unsigned long long *d_maxdef = nullptr;
+    double *d_stage = nullptr;
+    int block = 256, xcd = 1;
+    uint32_t upd_blocks = 0, plq_blocks = 0;
+    bool use_graph = true;
+    GraphCache graph;
+    std::vector<hipEvent_t> events;
+    int num_cus = 0;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+void drop_graph(su3hb_lattice *L)
+{
+    if (L->graph.exec) hipGraphExecDestroy(L->graph.exec);
+    if (L->graph.graph) hipGraphDestroy(L->graph.graph);
+    L->graph = GraphCache{};
+}
+
+// Block tables and offsets of every replica for the current launch shape.
+void layout_reps(su3hb_lattice *L)
+{
+    uint64_t off = 0;
+    uint32_t ub = 0, pb = 0;
+    const int NE = elems_per_link(L->prec);
+    for (auto &r : L->reps) {
+        r.elem_offset = off;
+        off += uint64_t(r.nlat) * L->nd * NE * r.V;
+        r.upd_block0 = ub;
+        r.upd_blocks = (r.nlat * r.Vh + L->block - 1) / L->block;
+        ub += r.upd_blocks;
+        // a few sites per plaquette thread keeps the partial sums to about
+        // 2048 blocks per lattice, which the finalize pass adds up quickly
+        const uint32_t nsite = r.nlat * r.V;
+        r.plq_spt = std::min<uint32_t>(16, std::max<uint32_t>(1, nsite / (uint32_t(kPlaqBlock) * 2048u)));
+        r.plq_block0 = pb;
+        r.plq_blocks = (nsite + kPlaqBlock * r.plq_spt - 1) / (kPlaqBlock * r.plq_spt);
+        pb += r.plq_blocks;
+    }
+    L->upd_blocks = ub;
+    L->plq_blocks = pb;
+}
+
+int upload_reps(su3hb_lattice *L)
+{
+    HIPCHK(hipMemcpyAsync(L->d_reps, L->reps.data(), sizeof(RepDesc) * L->reps.size(), hipMemcpyHostToDevice,
+                          L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return SU3HB_OK;
+}
+
+int check_extents(int nd, const int *ext, uint64_t *V)
+{
+    if (nd < SU3HB_GPU_MIN_D || nd > SU3HB_GPU_MAX_D)
+        return fail(SU3HB_EINVAL, "nd = %d outside %d..%d", nd, SU3HB_GPU_MIN_D, SU3HB_GPU_MAX_D);
+    uint64_t v = 1;
+    for (int i = 0; i < nd; ++i) {
+        if (ext[i] < 2 || (ext[i] & 1))
+            return fail(SU3HB_EINVAL, "extent %d of direction %d must be even and >= 2", ext[i], i);
+        v *= uint64_t(ext[i]);
+        if (v > (uint64_t(1) << 32)) return fail(SU3HB_EINVAL, "lattice volume exceeds 2^32 sites");
+    }
+    *V = v;
+    return SU3HB_OK;
+}
+
+RepDesc make_rep(int nd, const int *ext, int nlat, unsigned glued, int lat2test, uint64_t seed, double b0,
+                 double b1)
+{
+    RepDesc r;
+    std::memset(&r, 0, sizeof r);
+    uint32_t st = 1;
+    for (int i = 0; i < nd; ++i) {
+        r.n[i] = ext[i];
+        r.stride[i] = st;
+        st *= uint32_t(ext[i]);
+    }
+    r.V = st;
+    r.Vh = st / 2;
+    r.nlat = uint32_t(nlat);
+    r.glued = glued;
+    r.lat2test = uint32_t(lat2test);
+    r.key0 = uint32_t(seed);
+    r.key1 = uint32_t(seed >> 32);
+    r.beta0 = b0;
+    r.beta1 = b1;
+    return r;
+}
+
+int alloc_common(su3hb_lattice *L)
+{
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDevice(&L->device));
+    HIPCHK(hipGetDeviceProperties(&prop, L->device));
+    L->num_cus = prop.multiProcessorCount;
+    HIPCHK(hipStreamCreateWithFlags(&L->cap, hipStreamNonBlocking));
+    HIPCHK(hipMalloc(&L->d_reps, sizeof(RepDesc) * L->reps.size()));
+    HIPCHK(hipMalloc(&L->d_sweep, sizeof(uint32_t)));
+    HIPCHK(hipMalloc(&L->d_stats, sizeof(StatSlot) * kStatSlots));
+    HIPCHK(hipMalloc(&L->d_stats_out, sizeof(StatSlot)));
+    HIPCHK(hipMalloc(&L->d_plaq, sizeof(double) * 6 * L->reps.size()));
+    HIPCHK(hipMalloc(&L->d_series, sizeof(double) * 6 * kSeriesCap));
+    HIPCHK(hipMalloc(&L->d_cursor, sizeof(uint32_t)));
+    HIPCHK(hipMalloc(&L->d_maxdef, sizeof(unsigned long long)));
+    layout_reps(L);
+    HIPCHK(hipMalloc(&L->d_partials, sizeof(double) * 5 * L->plq_blocks));
+    int rc = upload_reps(L);
+    if (rc) return rc;
+    HIPCHK(launch_counter_set(L->stream, L->d_sweep, 0));
+    HIPCHK(launch_counter_set(L->stream, L->d_cursor, 0));
+    HIPCHK(launch_stats_zero(L->stream, L->d_stats));
+    return SU3HB_OK;
+}
+
+int adopt_or_alloc_links(su3hb_lattice *L, void *borrowed, size_t borrowed_bytes)
+{
+    uint64_t elems = 0;
+    for (auto &r : L->reps) elems += uint64_t(r.nlat) * L->nd * elems_per_link(L->prec) * r.V;
+    L->links_bytes = size_t(elems) * bytes_per_elem(L->prec);
+    if (borrowed) {
+        if (borrowed_bytes < L->links_bytes)
+            return fail(SU3HB_EINVAL, "device buffer holds %zu bytes, the links need %zu", borrowed_bytes,
+                        L->links_bytes);
+        if (reinterpret_cast<uintptr_t>(borrowed) % 16)
+            return fail(SU3HB_EINVAL, "device buffer must be 16-byte aligned");
+        L->links = borrowed;
+        L->owns_links = false;
+    } else {
+        hipError_t e = hipMalloc(&L->links, L->links_bytes);
+        if (e != hipSuccess)
+            return fail(SU3HB_ENOMEM, "hipMalloc of %zu bytes for the links failed: %s", L->links_bytes,
+                        hipGetErrorString(e));
+        L->owns_links = true;
+    }
+    return SU3HB_OK;
+}
+
+void destroy(su3hb_lattice *L)
+{
+    if (!L) return;
+    hipSetDevice(L->device);
+    if (L->stream) hipStreamSynchronize(L->stream);
+    drop_graph(L);
+    for (auto e : L->events) hipEventDestroy(e);
+    if (L->owns_links && L->links) hipFree(L->links);
+    hipFree(L->d_reps);
+    hipFree(L->d_sweep);
+    hipFree(L->d_stats);
+    hipFree(L->d_stats_out);
+    hipFree(L->d_partials);
+    hipFree(L->d_plaq);
+    hipFree(L->d_series);
+    hipFree(L->d_cursor);
+    hipFree(L->d_maxdef);
+    hipFree(L->d_stage);
+    if (L->cap) hipStreamDestroy(L->cap);
+    delete L;
+}
+
+int start_replica(su3hb_lattice *L, int r, int mode)
+{
+    if (mode == SU3HB_START_NONE) return SU3HB_OK;
+    const RepDesc &rep = L->reps[r];
+    const uint32_t nthreads = rep.nlat * uint32_t(L->nd) * rep.V;
+    HIPCHK(launch_start(L->nd, L->prec, L->stream, L->links, L->d_reps, r, nthreads, mode));
+    return SU3HB_OK;
+}
+
+UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
+{
+    UpdateArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.links = L->links;
+    a.reps = L->d_reps;
+    a.nrep = L->nrep;
+    a.nhit = nhit;
+    a.use_rep_beta = L->batch ? 1 : 0;
+    a.xcd_remap = L->xcd;
+    a.beta0 = b0;
+    a.beta1 = b1;
+    a.sweep = L->d_sweep;
+    a.stats = L->d_stats;
+    a.total_blocks = L->upd_blocks;
+    return a;
+}
+
+dim3 update_grid(const su3hb_lattice *L)
+{
+    uint32_t g = L->upd_blocks;
+    if (L->xcd) g = (g + 7) / 8 * 8;
+    return dim3(g);
+}
+
+int enqueue_plaquette(su3hb_lattice *L, hipStream_t st, double b0, double b1, double *series)
+{
+    PlaqArgs pa;
+    std::memset(&pa, 0, sizeof pa);
+    pa.links = L->links;
+    pa.reps = L->d_reps;
+    pa.nrep = L->nrep;
+    pa.beta0 = b0;
+    pa.beta1 = b1;
+    pa.use_rep_beta = L->batch ? 1 : 0;
+    pa.partials = L->d_partials;
+    pa.total_blocks = L->plq_blocks;
+    HIPCHK(launch_plaquette(L->nd, L->prec, dim3(L->plq_blocks), dim3(kPlaqBlock), st, pa));
+    HIPCHK(launch_plaquette_finalize(st, L->d_reps, L->nrep, L->nd, L->d_partials, L->d_plaq, series,
+                                     L->d_cursor));
+    return SU3HB_OK;
+}
+
+// One sweep: parity 0 then 1, directions 0..D-1 inside, then the counter.
+int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nhit, int measure)
+{
+    UpdateArgs a = update_args(L, b0, b1, nhit);
+    const dim3 grid = update_grid(L), block(L->block);
+    for (int p = 0; p < 2; ++p)
+        for (int mu = 0; mu < L->nd; ++mu) {
+            a.parity = p;
+            a.mu = mu;
+            HIPCHK(launch_update(L->nd, L->prec, grid, block, st, a));
+        }
+    HIPCHK(launch_counter_add(st, L->d_sweep, 1));
+    if (measure) return enqueue_plaquette(L, st, b0, b1, L->d_series);
+    return SU3HB_OK;
+}
+
+int get_graph(su3hb_lattice *L, double b0, double b1, int nhit, int measure)
+{
+    GraphCache &g = L->graph;
+    if (g.valid && g.b0 == b0 && g.b1 == b1 && g.nhit == nhit && g.measure == measure) return SU3HB_OK;
+    drop_graph(L);
+    HIPCHK(hipStreamBeginCapture(L->cap, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_sweep(L, L->cap, b0, b1, nhit, measure);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(L->cap, &graph);
+    if (rc) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(SU3HB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(SU3HB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    g.valid = true;
+    g.b0 = b0;
+    g.b1 = b1;
+    g.nhit = nhit;
+    g.measure = measure;
+    g.graph = graph;
+    g.exec = exec;
+    return SU3HB_OK;
+}
+
+int run_sweeps(su3hb_lattice *L, double b0, double b1, int nhit, int n, int measure)
+{
+    if (n <= 0) return SU3HB_OK;
+    if (L->use_graph) {
+        int rc = get_graph(L, b0, b1, nhit, measure);
+        if (rc) return rc;
+        for (int i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(L->graph.exec, L->stream));
+    } else {
+        for (int i = 0; i < n; ++i) {
+            int rc = enqueue_sweep(L, L->stream, b0, b1, nhit, measure);
+            if (rc) return rc;
+        }
+    }
+    L->sweep += uint64_t(n);
+    return SU3HB_OK;
+}
+
+int read_stats(su3hb_lattice *L, su3hb_stats *out)
+{
+    StatSlot s;
+    HIPCHK(launch_stats_reduce(L->stream, L->d_stats, L->d_stats_out));
+    HIPCHK(hipMemcpyAsync(&s, L->d_stats_out, sizeof s, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    for (int i = 0; i < 3; ++i) {
+        out->attempts[i] = s.attempts[i];
+        out->accepts[i] = s.accepts[i];
+    }
+    out->link_updates = s.updates;
+    out->dtrace = s.dtrace;
+    return SU3HB_OK;
+}
+
+int check_sweep_args(double b0, double b1, int nhit, int n)
+{
+    if (!std::isfinite(b0) || !std::isfinite(b1)) return fail(SU3HB_EINVAL, "beta must be finite");
+    if (nhit < 1 || nhit > 32767) return fail(SU3HB_EINVAL, "n_hit = %d outside 1..32767", nhit);
+    if (n < 0) return fail(SU3HB_EINVAL, "n_sweeps = %d is negative", n);
+    return SU3HB_OK;
+}
+
+int ensure_stage(su3hb_lattice *L)
+{
+    if (!L->d_stage) {
+        hipError_t e = hipMalloc(&L->d_stage, kStageBytes);
+        if (e != hipSuccess) return fail(SU3HB_ENOMEM, "staging buffer: %s", hipGetErrorString(e));
+    }
+    return SU3HB_OK;
+}
+
+int get_replica_links(su3hb_lattice *L, int r, double *host, size_t n)
+{
+    const RepDesc &rep = L->reps[r];
+    const uint64_t nsites = uint64_t(rep.nlat) * rep.V;
+    const size_t per_site = size_t(L->nd) * 18;
+    if (!host) return fail(SU3HB_EINVAL, "host buffer is NULL");
+    if (n != nsites * per_site)
+        return fail(SU3HB_EINVAL, "n = %zu, expected nlat*V*D*18 = %zu", n, size_t(nsites * per_site));
+    int rc = ensure_stage(L);
+    if (rc) return rc;
+    const uint64_t chunk = kStageBytes / (per_site * sizeof(double));
+    for (uint64_t c0 = 0; c0 < nsites; c0 += chunk) {
+        const uint32_t cnt = uint32_t(std::min<uint64_t>(chunk, nsites - c0));
+        HIPCHK(launch_pack(L->nd, L->prec, L->stream, L->links, L->d_reps, r, c0, cnt, L->d_stage));
+        HIPCHK(hipMemcpyAsync(host + c0 * per_site, L->d_stage, size_t(cnt) * per_site * sizeof(double),
+                              hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    return SU3HB_OK;
+}
+
+int set_replica_links(su3hb_lattice *L, int r, const double *host, size_t n)
+{
+    const RepDesc &rep = L->reps[r];
+    const uint64_t nsites = uint64_t(rep.nlat) * rep.V;
+    const size_t per_site = size_t(L->nd) * 18;
+    if (!host) return fail(SU3HB_EINVAL, "host buffer is NULL");
+    if (n != nsites * per_site)
+        return fail(SU3HB_EINVAL, "n = %zu, expected nlat*V*D*18 = %zu", n, size_t(nsites * per_site));
+    int rc = ensure_stage(L);
+    if (rc) return rc;
+    const double tol = L->prec == kFP64_18 ? 1e-10 : 1e-6;
+    const uint64_t chunk = kStageBytes / (per_site * sizeof(double));
+    const bool single = nsites <= chunk;
+    // pass 1: validate every matrix on the GPU before anything is written
+    HIPCHK(launch_u64_zero(L->stream, L->d_maxdef, 1));
+    for (uint64_t c0 = 0; c0 < nsites; c0 += chunk) {
+        const uint32_t cnt = uint32_t(std::min<uint64_t>(chunk, nsites - c0));
+        HIPCHK(hipMemcpyAsync(L->d_stage, host + c0 * per_site, size_t(cnt) * per_site * sizeof(double),
+                              hipMemcpyHostToDevice, L->stream));
+        HIPCHK(launch_validate(L->stream, L->d_stage, uint64_t(cnt) * L->nd, L->d_maxdef));
+        if (!single) HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, L->d_maxdef, sizeof bits, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    double maxdef;
+    std::memcpy(&maxdef, &bits, sizeof maxdef);
+    if (!(maxdef <= tol))
+        return fail(SU3HB_ENOTSU3, "input is not SU(3): max defect %.3g exceeds %.1g", maxdef, tol);
+    // pass 2: convert into the internal storage
+    for (uint64_t c0 = 0; c0 < nsites; c0 += chunk) {
+        const uint32_t cnt = uint32_t(std::min<uint64_t>(chunk, nsites - c0));
+        if (!single)
+            HIPCHK(hipMemcpyAsync(L->d_stage, host + c0 * per_site, size_t(cnt) * per_site * sizeof(double),
+                                  hipMemcpyHostToDevice, L->stream));
+        HIPCHK(launch_unpack(L->nd, L->prec, L->stream, L->links, L->d_reps, r, c0, cnt, L->d_stage));
+        HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    return SU3HB_OK;
+}
+
+std::string tune_key(const su3hb_lattice *L)
+{
+    std::string k = std::to_string(L->prec) + ":" + std::to_string(L->nd);
+    for (auto &r : L->reps) {
+        k += "|";
+        for (int i = 0; i < L->nd; ++i) k += std::to_string(r.n[i]) + ",";
+        k += std::to_string(r.nlat);
+    }
+    return k;
+}
+
+int apply_launch(su3hb_lattice *L, int block, int xcd)
+{
+    if (block != 64 && block != 128 && block != 256)
+        return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
+    HIPCHK(hipStreamSynchronize(L->stream));
+    drop_graph(L);
+    L->block = block;
+    L->xcd = xcd ? 1 : 0;
+    layout_reps(L);
+    return upload_reps(L);
+}
+
+int ensure_events(su3hb_lattice *L, size_t n)
+{
+    while (L->events.size() < n) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        L->events.push_back(e);
+    }
+    return SU3HB_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *su3hb_last_error(void) { return g_err.c_str(); }
+
+int su3hb_links_bytes(const su3hb_params *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SU3HB_EINVAL, "NULL argument");
+    uint64_t V;
+    int rc = check_extents(p->nd, p->extents, &V);
+    if (rc) return rc;
+    if (p->nlat != 1 && p->nlat != 2) return fail(SU3HB_EINVAL, "nlat = %d, expected 1 or 2", p->nlat);
+    if (p->precision < 0 || p->precision > 2) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
+    *bytes = size_t(p->nlat) * p->nd * V * size_t(bytes_per_link(p->precision));
+    return SU3HB_OK;
+}
+
+int su3hb_init_lattice(su3hb_lattice **out, const su3hb_params *p)
+{
+    if (!out) return fail(SU3HB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(SU3HB_EINVAL, "params is NULL");
+    uint64_t V;
+    int rc = check_extents(p->nd, p->extents, &V);
+    if (rc) return rc;
+    if (p->nlat != 1 && p->nlat != 2) return fail(SU3HB_EINVAL, "nlat = %d, expected 1 or 2", p->nlat);
+    if (p->nlat == 1 && (p->dlt_mask != 0 || p->lat2test))
+        return fail(SU3HB_EINVAL, "dlt_mask and lat2test need nlat = 2");
+    if (p->dlt_mask >> p->nd) return fail(SU3HB_EINVAL, "dlt_mask has bits beyond direction %d", p->nd - 1);
+    if (p->precision < 0 || p->precision > 2) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
+    if (p->start < 0 || p->start > 2) return fail(SU3HB_EINVAL, "unknown start %d", p->start);
+    if (double(p->nlat) * double(V) * p->nd > 4294967295.0)
+        return fail(SU3HB_EINVAL, "more than 2^32 links: the Philox counter holds a 32-bit link id");
+
+    su3hb_lattice *L = new su3hb_lattice;
+    L->nd = p->nd;
+    L->prec = p->precision;
+    L->nrep = 1;
+    L->batch = false;
+    L->seed = p->seed;
+    L->stream = reinterpret_cast<hipStream_t>(p->hip_stream);
+    L->reps.push_back(make_rep(p->nd, p->extents, p->nlat, p->nlat == 2 ? p->dlt_mask : 0u, p->lat2test,
+                               p->seed, 0.0, 0.0));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(L));
+        if (it != g_tune_cache.end()) {
+            L->block = it->second.first;
+            L->xcd = it->second.second;
+        }
+    }
+    rc = adopt_or_alloc_links(L, p->device_links, p->device_bytes);
+    if (!rc) rc = alloc_common(L);
+    if (!rc) rc = start_replica(L, 0, p->start);
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(L->stream);
+        if (e != hipSuccess) rc = fail(SU3HB_EHIP, "init: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        destroy(L);
+        return rc;
+    }
+    *out = L;
+    return SU3HB_OK;
+}
+
+void su3hb_free(su3hb_lattice *lat) { destroy(lat); }
+
+int su3hb_sweep(su3hb_lattice *L, double beta0, double beta1, int n_hit, int n_sweeps, su3hb_stats *stats)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    int rc = check_sweep_args(beta0, beta1, n_hit, n_sweeps);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(L->device));
+    if (stats) HIPCHK(launch_stats_zero(L->stream, L->d_stats));
+    rc = run_sweeps(L, beta0, beta1, n_hit, n_sweeps, 0);
+    if (rc) return rc;
+    if (stats) return read_stats(L, stats);
+    return SU3HB_OK;
+}
+
+int su3hb_sweep_measure(su3hb_lattice *L, double beta0, double beta1, int n_hit, int n_sweeps, double *series,
+                        su3hb_stats *stats)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (L->batch) return fail(SU3HB_EINVAL, "use su3hb_batch_plaquette for batches");
+    if (!series && n_sweeps > 0) return fail(SU3HB_EINVAL, "series is NULL");
+    int rc = check_sweep_args(beta0, beta1, n_hit, n_sweeps);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(L->device));
+    if (stats) HIPCHK(launch_stats_zero(L->stream, L->d_stats));
+    for (int done = 0; done < n_sweeps;) {
+        const int chunk = std::min<int>(int(kSeriesCap), n_sweeps - done);
+        HIPCHK(launch_counter_set(L->stream, L->d_cursor, 0));
+        rc = run_sweeps(L, beta0, beta1, n_hit, chunk, 1);
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(series + size_t(done) * 6, L->d_series, sizeof(double) * 6 * chunk,
+                              hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+        done += chunk;
+    }
+    if (stats) return read_stats(L, stats);
+    return SU3HB_OK;
+}
+
+int su3hb_plaquette(su3hb_lattice *L, double beta0, double beta1, double out[6])
+{
+    if (!L || !out) return fail(SU3HB_EINVAL, "NULL argument");
+    if (L->batch) return fail(SU3HB_EINVAL, "use su3hb_batch_plaquette for batches");
+    HIPCHK(hipSetDevice(L->device));
+    int rc = enqueue_plaquette(L, L->stream, beta0, beta1, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(out, L->d_plaq, sizeof(double) * 6, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return SU3HB_OK;
+}
+
+int su3hb_get_links(const su3hb_lattice *Lc, double *host, size_t n)
+{
+    su3hb_lattice *L = const_cast<su3hb_lattice *>(Lc);
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (L->batch) return fail(SU3HB_EINVAL, "use su3hb_batch_get_links for batches");
+    HIPCHK(hipSetDevice(L->device));
+    return get_replica_links(L, 0, host, n);
+}
+
+int su3hb_set_links(su3hb_lattice *L, const double *host, size_t n)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (L->batch) return fail(SU3HB_EINVAL, "use su3hb_batch_set_links for batches");
+    HIPCHK(hipSetDevice(L->device));
+    return set_replica_links(L, 0, host, n);
+}
+
+int su3hb_get_state(const su3hb_lattice *L, uint64_t *seed, uint64_t *sweep)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (seed) *seed = L->seed;
+    if (sweep) *sweep = L->sweep;
+    return SU3HB_OK;
+}
+
+int su3hb_set_state(su3hb_lattice *L, uint64_t seed, uint64_t sweep)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (L->batch) return fail(SU3HB_EINVAL, "batches keep one seed per replica");
+    HIPCHK(hipSetDevice(L->device));
+    L->seed = seed;
+    L->reps[0].key0 = uint32_t(seed);
+    L->reps[0].key1 = uint32_t(seed >> 32);
+    int rc = upload_reps(L);
+    if (rc) return rc;
+    L->sweep = sweep;
+    HIPCHK(launch_counter_set(L->stream, L->d_sweep, uint32_t(sweep)));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return SU3HB_OK;
+}
+
+int su3hb_set_launch(su3hb_lattice *L, int block, int xcd_remap)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    HIPCHK(hipSetDevice(L->device));
+    return apply_launch(L, block, xcd_remap);
+}
+
+int su3hb_get_launch(const su3hb_lattice *L, int *block, int *xcd_remap)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (block) *block = L->block;
+    if (xcd_remap) *xcd_remap = L->xcd;
+    return SU3HB_OK;
+}
+
+int su3hb_autotune(su3hb_lattice *L, int budget_ms)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    if (budget_ms < 1) return fail(SU3HB_EINVAL, "budget_ms must be positive");
+    HIPCHK(hipSetDevice(L->device));
+    const std::string key = tune_key(L);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return apply_launch(L, it->second.first, it->second.second);
+    }
+    // keep the state: links, sweep counter and statistics are restored below
+    void *backup = nullptr;
+    hipError_t e = hipMalloc(&backup, L->links_bytes);
+    if (e != hipSuccess) return fail(SU3HB_ENOMEM, "autotune backup: %s", hipGetErrorString(e));
+    struct Free {
+        void *p;
+        ~Free() { hipFree(p); }
+    } guard{backup};
+    HIPCHK(hipMemcpyAsync(backup, L->links, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
+    const uint64_t sweep0 = L->sweep;
+    const int cands[6][2] = {{256, 1}, {128, 1}, {64, 1}, {256, 0}, {128, 0}, {64, 0}};
+    const double b = L->batch ? 0.0 : 6.0;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_i = 0;
+    const bool graph = L->use_graph;
+    L->use_graph = false;
+    int rc = SU3HB_OK;
+    for (int i = 0; i < 6 && !rc; ++i) {
+        rc = apply_launch(L, cands[i][0], cands[i][1]);
+        if (rc) break;
+        rc = enqueue_sweep(L, L->stream, b, b, 8, 0);  // warm-up
+        if (rc) break;
+        int reps = 1;
+        float ms = 0.f;
+        for (;;) {
+            if (hipEventRecord(e0, L->stream) != hipSuccess) { rc = fail(SU3HB_EHIP, "event"); break; }
+            for (int k = 0; k < reps && !rc; ++k) rc = enqueue_sweep(L, L->stream, b, b, 8, 0);
+            if (rc) break;
+            if (hipEventRecord(e1, L->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(SU3HB_EHIP, "event");
+                break;
+            }
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms * 6 * 2 >= budget_ms || reps >= 64) break;
+            reps *= 2;
+        }
+        if (rc) break;
+        const float per = ms / reps;
+        if (per < best) {
+            best = per;
+            best_i = i;
+        }
+    }
+    L->use_graph = graph;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    HIPCHK(hipMemcpyAsync(L->links, backup, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
+    HIPCHK(launch_counter_set(L->stream, L->d_sweep, uint32_t(sweep0)));
+    HIPCHK(launch_stats_zero(L->stream, L->d_stats));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->sweep = sweep0;
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {cands[best_i][0], cands[best_i][1]};
+    }
+    return apply_launch(L, cands[best_i][0], cands[best_i][1]);
+}
+
+int su3hb_sweep_timed(su3hb_lattice *L, double beta0, double beta1, int n_hit, int n_sweeps, int measure,
+                      double *series, double timing[4])
+{
+    if (!L || !timing) return fail(SU3HB_EINVAL, "NULL argument");
+    if (L->batch && measure) return fail(SU3HB_EINVAL, "batches measure with su3hb_batch_plaquette");
+    if (measure && !series && n_sweeps > 0) return fail(SU3HB_EINVAL, "series is NULL");
+    if (measure && n_sweeps > int(kSeriesCap))
+        return fail(SU3HB_EINVAL, "at most %u measured sweeps per call", kSeriesCap);
+    int rc = check_sweep_args(beta0, beta1, n_hit, n_sweeps);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(L->device));
+    const size_t upd_per = size_t(2 * L->nd), launches = size_t(n_sweeps) * (upd_per + (measure ? 1 : 0));
+    rc = ensure_events(L, 2 * launches);
+    if (rc) return rc;
+    UpdateArgs a = update_args(L, beta0, beta1, n_hit);
+    const dim3 grid = update_grid(L), block(L->block);
+    if (measure) HIPCHK(launch_counter_set(L->stream, L->d_cursor, 0));
+    size_t ev = 0;
+    std::vector<int> is_plaq;
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        for (int p = 0; p < 2; ++p)
+            for (int mu = 0; mu < L->nd; ++mu) {
+                a.parity = p;
+                a.mu = mu;
+                HIPCHK(hipEventRecord(L->events[ev], L->stream));
+                HIPCHK(launch_update(L->nd, L->prec, grid, block, L->stream, a));
+                HIPCHK(hipEventRecord(L->events[ev + 1], L->stream));
+                ev += 2;
+                is_plaq.push_back(0);
+            }
+        HIPCHK(launch_counter_add(L->stream, L->d_sweep, 1));
+        if (measure) {
+            PlaqArgs pa;
+            std::memset(&pa, 0, sizeof pa);
+            pa.links = L->links;
+            pa.reps = L->d_reps;
+            pa.nrep = L->nrep;
+            pa.beta0 = beta0;
+            pa.beta1 = beta1;
+            pa.use_rep_beta = L->batch ? 1 : 0;
+            pa.partials = L->d_partials;
+            pa.total_blocks = L->plq_blocks;
+            HIPCHK(hipEventRecord(L->events[ev], L->stream));
+            HIPCHK(launch_plaquette(L->nd, L->prec, dim3(L->plq_blocks), dim3(kPlaqBlock), L->stream, pa));
+            HIPCHK(hipEventRecord(L->events[ev + 1], L->stream));
+            ev += 2;
+            is_plaq.push_back(1);
+            HIPCHK(launch_plaquette_finalize(L->stream, L->d_reps, L->nrep, L->nd, L->d_partials, L->d_plaq,
+                                             L->d_series, L->d_cursor));
+        }
+    }
+    L->sweep += uint64_t(n_sweeps);
+    HIPCHK(hipStreamSynchronize(L->stream));
+    double t_upd = 0, t_plq = 0, n_upd = 0, n_plq = 0;
+    for (size_t i = 0; i < is_plaq.size(); ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, L->events[2 * i], L->events[2 * i + 1]));
+        if (is_plaq[i]) {
+            t_plq += ms;
+            n_plq += 1;
+        } else {
+            t_upd += ms;
+            n_upd += 1;
+        }
+    }
+    timing[0] = t_upd;
+    timing[1] = n_upd;
+    timing[2] = t_plq;
+    timing[3] = n_plq;
+    if (measure && n_sweeps > 0) {
+        HIPCHK(hipMemcpyAsync(series, L->d_series, sizeof(double) * 6 * n_sweeps, hipMemcpyDeviceToHost,
+                              L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    return SU3HB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+
+int su3hb_batch_create(su3hb_batch **out, int nd, const su3hb_replica_desc *reps, int n, int precision,
+                       void *hip_stream)
+{
+    if (!out) return fail(SU3HB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!reps || n < 1) return fail(SU3HB_EINVAL, "need at least one replica");
+    if (precision < 0 || precision > 2) return fail(SU3HB_EINVAL, "unknown precision %d", precision);
+    double links = 0;
+    for (int r = 0; r < n; ++r) {
+        uint64_t V;
+        int rc = check_extents(nd, reps[r].extents, &V);
+        if (rc) return fail(rc, "replica %d: %s", r, g_err.c_str());
+        if (!std::isfinite(reps[r].beta)) return fail(SU3HB_EINVAL, "replica %d: beta not finite", r);
+        if (reps[r].start < 0 || reps[r].start > 2) return fail(SU3HB_EINVAL, "replica %d: bad start", r);
+        links += double(V) * nd;
+    }
+    (void)links;
+    su3hb_lattice *L = new su3hb_lattice;
+    L->nd = nd;
+    L->prec = precision;
+    L->nrep = n;
+    L->batch = true;
+    L->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int r = 0; r < n; ++r)
+        L->reps.push_back(make_rep(nd, reps[r].extents, 1, 0u, 0, reps[r].seed, reps[r].beta, reps[r].beta));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(L));
+        if (it != g_tune_cache.end()) {
+            L->block = it->second.first;
+            L->xcd = it->second.second;
+        }
+    }
+    int rc = adopt_or_alloc_links(L, nullptr, 0);
+    if (!rc) rc = alloc_common(L);
+    for (int r = 0; r < n && !rc; ++r) rc = start_replica(L, r, reps[r].start);
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(L->stream);
+        if (e != hipSuccess) rc = fail(SU3HB_EHIP, "batch init: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        destroy(L);
+        return rc;
+    }
+    *out = L;
+    return SU3HB_OK;
+}
+
+int su3hb_batch_sweep(su3hb_batch *L, int n_hit, int n_sweeps, int mode, su3hb_stats *stats)
+{
+    if (!L || !L->batch) return fail(SU3HB_EINVAL, "not a batch");
+    int rc = check_sweep_args(0.0, 0.0, n_hit, n_sweeps);
+    if (rc) return rc;
+    if (mode != 0 && mode != 1) return fail(SU3HB_EINVAL, "mode = %d, expected 0 or 1", mode);
+    HIPCHK(hipSetDevice(L->device));
+    if (stats) HIPCHK(launch_stats_zero(L->stream, L->d_stats));
+    if (mode == 0) {
+        rc = run_sweeps(L, 0.0, 0.0, n_hit, n_sweeps, 0);
+        if (rc) return rc;
+    } else if (n_sweeps > 0) {
+        int per_cu = 0;
+        HIPCHK(persistent_max_blocks(L->nd, L->prec, L->block, &per_cu));
+        if (per_cu < 1) return fail(SU3HB_EUNSUPPORTED, "persistent kernel cannot be resident");
+        const int blocks = int(std::min<uint64_t>(uint64_t(per_cu) * L->num_cus, L->upd_blocks));
+        UpdateArgs a = update_args(L, 0.0, 0.0, n_hit);
+        a.xcd_remap = 0;
+        HIPCHK(launch_update_persistent(L->nd, L->prec, blocks, L->block, L->stream, a, n_sweeps));
+        HIPCHK(launch_counter_add(L->stream, L->d_sweep, uint32_t(n_sweeps)));
+        L->sweep += uint64_t(n_sweeps);
+    }
+    if (stats) return read_stats(L, stats);
+    return SU3HB_OK;
+}
+
+int su3hb_batch_plaquette(su3hb_batch *L, double *out, size_t n)
+{
+    if (!L || !L->batch || !out) return fail(SU3HB_EINVAL, "bad arguments");
+    if (n != size_t(L->nrep) * 6) return fail(SU3HB_EINVAL, "n = %zu, expected 6 per replica", n);
+    HIPCHK(hipSetDevice(L->device));
+    int rc = enqueue_plaquette(L, L->stream, 0.0, 0.0, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(out, L->d_plaq, sizeof(double) * n, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return SU3HB_OK;
+}
+
+int su3hb_batch_get_links(su3hb_batch *L, int replica, double *host, size_t n)
+{
+    if (!L || !L->batch) return fail(SU3HB_EINVAL, "not a batch");
+    if (replica < 0 || replica >= L->nrep) return fail(SU3HB_EINVAL, "replica %d out of range", replica);
+    HIPCHK(hipSetDevice(L->device));
+    return get_replica_links(L, replica, host, n);
+}
+
+int su3hb_batch_set_links(su3hb_batch *L, int replica, const double *host, size_t n)
+{
+    if (!L || !L->batch) return fail(SU3HB_EINVAL, "not a batch");
+    if (replica < 0 || replica >= L->nrep) return fail(SU3HB_EINVAL, "replica %d out of range", replica);
+    HIPCHK(hipSetDevice(L->device));
+    return set_replica_links(L, replica, host, n);
+}
+
+void su3hb_batch_free(su3hb_batch *b) { destroy(b); }
+
+}  // extern "C"

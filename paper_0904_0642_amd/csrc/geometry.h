@@ -1,0 +1,95 @@
+// geometry.h -- per-thread lattice geometry for the kernels: coordinates of a
+// checkerboard site from its half-lattice index, neighbour site numbers with
+// periodic wrap or the layer flip of the double-layered torus, link pointers.
+#pragma once
+
+#include "device_math.h"
+
+namespace su3hb {
+
+// Find the replica owning logical block lb: largest r with first[r] <= lb.
+// The block index and the table are uniform, so this runs on scalar units.
+__device__ __forceinline__ int find_replica(const RepDesc *__restrict__ reps, int nrep, uint32_t lb,
+                                            bool plaquette)
+{
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const uint32_t first = plaquette ? reps[mid].plq_block0 : reps[mid].upd_block0;
+        if (first <= lb) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A site of parity p given by its half index h (site number s = 2h + b).
+// Eq. (i_s) with direction 0 fastest: since n0 is even, sites 2h and 2h+1
+// share x1..x_{D-1} and have opposite parity, so h indexes each checkerboard.
+template <int D>
+struct Site {
+    int x[D];
+    uint32_t s;
+    uint32_t layer;
+
+    __device__ __forceinline__ void from_half(const RepDesc &rep, uint32_t h, int p, uint32_t lay)
+    {
+        const uint32_t nh0 = uint32_t(rep.n[0]) >> 1;
+        uint32_t rest = h / nh0;
+        const uint32_t hx = h - rest * nh0;
+        int psum = p;
+#pragma unroll
+        for (int i = 1; i < D; ++i) {
+            if (i < D - 1) {
+                const uint32_t q = rest / uint32_t(rep.n[i]);
+                x[i] = int(rest - q * uint32_t(rep.n[i]));
+                rest = q;
+            } else {
+                x[i] = int(rest);
+            }
+            psum += x[i];
+        }
+        x[0] = int(2 * hx) + (psum & 1);
+        s = 2 * h + uint32_t(psum & 1);
+        layer = lay;
+    }
+};
+
+// Site-number offset and layer of one step along +dir or -dir.
+struct Step {
+    int32_t ds;       // change of the site number
+    uint32_t flip;    // 1 if the step changes layer
+};
+
+template <int D>
+__device__ __forceinline__ Step step_fwd(const RepDesc &rep, const Site<D> &x, int dir, uint32_t glued)
+{
+    const bool wrap = x.x[dir] == rep.n[dir] - 1;
+    Step st;
+    st.ds = wrap ? -int32_t((rep.n[dir] - 1) * rep.stride[dir]) : int32_t(rep.stride[dir]);
+    st.flip = wrap ? ((glued >> dir) & 1u) : 0u;
+    return st;
+}
+
+template <int D>
+__device__ __forceinline__ Step step_bwd(const RepDesc &rep, const Site<D> &x, int dir, uint32_t glued)
+{
+    const bool wrap = x.x[dir] == 0;
+    Step st;
+    st.ds = wrap ? int32_t((rep.n[dir] - 1) * rep.stride[dir]) : -int32_t(rep.stride[dir]);
+    st.flip = wrap ? ((glued >> dir) & 1u) : 0u;
+    return st;
+}
+
+// Pointer to element 0 of link (layer, dir) at the site with number s and
+// parity par; elements follow at stride Vh.
+template <int D, int PREC>
+__device__ __forceinline__ typename Store<PREC>::elem *link_ptr(void *links, const RepDesc &rep,
+                                                                 uint32_t layer, int dir, int par,
+                                                                 uint32_t s)
+{
+    using E = typename Store<PREC>::elem;
+    constexpr int NE = Store<PREC>::NE;
+    const size_t slab = size_t((layer * D + uint32_t(dir)) * 2u + uint32_t(par)) * NE * rep.Vh;
+    return reinterpret_cast<E *>(links) + rep.elem_offset + slab + (s >> 1);
+}
+
+}  // namespace su3hb

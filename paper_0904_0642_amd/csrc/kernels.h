@@ -1,0 +1,45 @@
+// kernels.h -- host-callable launchers of the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace su3hb {
+
+// checkerboard slice update (one colour, one direction, all replicas)
+hipError_t launch_update(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a);
+
+// persistent cooperative batch sweep: n_sweeps x 2D slices with a grid barrier
+hipError_t launch_update_persistent(int D, int prec, int blocks, int threads, hipStream_t st,
+                                    const UpdateArgs &a, int n_sweeps);
+hipError_t persistent_max_blocks(int D, int prec, int threads, int *blocks_per_cu);
+
+// plaquettes: per-block partial sums, then one block per replica finalises
+hipError_t launch_plaquette(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const PlaqArgs &a);
+hipError_t launch_plaquette_finalize(hipStream_t st, const RepDesc *reps, int nrep, int D,
+                                     const double *partials, double *out, double *series,
+                                     uint32_t *series_cursor);
+
+// start configuration of one replica: mode 1 ordered, 2 Haar
+hipError_t launch_start(int D, int prec, hipStream_t st, void *links, const RepDesc *reps, int r,
+                        uint32_t nthreads, int mode);
+
+// canonical FP64 [layer][site][mu][3][3] <-> internal storage, for the sites
+// [c0, c0 + count) of the flat (layer * V + site) range of replica r
+hipError_t launch_pack(int D, int prec, hipStream_t st, const void *links, const RepDesc *reps, int r,
+                       uint64_t c0, uint32_t count, double *dst);
+hipError_t launch_unpack(int D, int prec, hipStream_t st, void *links, const RepDesc *reps, int r,
+                         uint64_t c0, uint32_t count, const double *src);
+// max over matrices of max(|U U^dag - 1|, |det U - 1|) as the bits of a
+// non-negative double (Inf for non-finite input), folded into *maxdef
+hipError_t launch_validate(hipStream_t st, const double *src, uint64_t nmat, unsigned long long *maxdef);
+
+// statistics slots and counters
+hipError_t launch_stats_zero(hipStream_t st, StatSlot *slots);
+hipError_t launch_stats_reduce(hipStream_t st, const StatSlot *slots, StatSlot *out);
+hipError_t launch_counter_add(hipStream_t st, uint32_t *ctr, uint32_t add);
+hipError_t launch_counter_set(hipStream_t st, uint32_t *ctr, uint32_t value);
+hipError_t launch_u64_zero(hipStream_t st, unsigned long long *p, int n);
+
+}  // namespace su3hb

@@ -1,0 +1,75 @@
+// layout.h -- descriptors shared by the host side and the kernels of the GPU
+// library: storage modes, the per-replica descriptor and kernel arguments.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace su3hb {
+
+constexpr int kFP64_18 = 0;
+constexpr int kFP32_18 = 1;
+constexpr int kFP32_12 = 2;
+
+constexpr int kMaxD = 6;          // kernels are instantiated for D = 2 .. 6
+constexpr int kStatSlots = 256;   // spread of the per-block statistics atomics
+
+inline constexpr int elems_per_link(int prec) { return prec == kFP32_12 ? 6 : 9; }
+inline constexpr int bytes_per_elem(int prec) { return prec == kFP64_18 ? 16 : 8; }
+inline constexpr int bytes_per_link(int prec) { return elems_per_link(prec) * bytes_per_elem(prec); }
+
+// One lattice ("replica").  A single lattice is a batch of one.  Its links
+// start `elem_offset` complex elements into the batch's link buffer and are
+// laid out as [layer][mu][parity][element][Vh].
+struct RepDesc {
+    uint64_t elem_offset;
+    int32_t n[kMaxD];        // extents
+    uint32_t stride[kMaxD];  // site-number strides: 1, n0, n0 n1, ...
+    uint32_t V;              // sites per layer
+    uint32_t Vh;             // V / 2
+    uint32_t nlat;           // 1 or 2
+    uint32_t glued;          // dlt mask (only with nlat == 2)
+    uint32_t lat2test;
+    uint32_t key0, key1;     // Philox key (seed)
+    double beta0, beta1;     // couplings used when the batch carries them
+    uint32_t upd_block0;     // first block of this replica in an update launch
+    uint32_t upd_blocks;     // blocks of this replica in an update launch
+    uint32_t plq_block0;     // first block in a plaquette launch
+    uint32_t plq_blocks;
+    uint32_t plq_spt;        // sites per thread in the plaquette launch
+};
+
+// Statistics slot, padded to its own 128-byte line.
+struct alignas(128) StatSlot {
+    unsigned long long attempts[3];
+    unsigned long long accepts[3];
+    unsigned long long updates;
+    double dtrace;
+};
+
+struct UpdateArgs {
+    void *links;                 // base of the link buffer
+    const RepDesc *reps;         // device array
+    int nrep;
+    int parity;                  // checkerboard colour being updated
+    int mu;                      // direction being updated
+    int nhit;                    // KP proposals per subgroup, at most
+    int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
+    int xcd_remap;               // 1: renumber blocks XCD by XCD
+    double beta0, beta1;
+    const uint32_t *sweep;       // device sweep counter
+    StatSlot *stats;             // kStatSlots slots
+    uint32_t total_blocks;       // real blocks (grid may be padded to 8)
+};
+
+struct PlaqArgs {
+    const void *links;
+    const RepDesc *reps;
+    int nrep;
+    double beta0, beta1;
+    int use_rep_beta;
+    double *partials;            // [block][5]
+    uint32_t total_blocks;
+};
+
+}  // namespace su3hb

@@ -1,0 +1,330 @@
+// update.hip -- the checkerboard slice update: for one colour p and one
+// direction mu, every link U_mu(x) with parity(x) = p in every layer of every
+// replica receives one Cabibbo-Marinari heatbath update (paper Sec. 1, 2.1):
+//   staple A (beta-weighted, Sec. 2.2 tag rule) -> W = U A ->
+//   SU(2) subgroups (0,1), (0,2), (1,2): project W, Kennedy-Pendleton draw of
+//   x0 in multi-hit form (at most n_hit proposals; none accepted keeps the
+//   link), random direction, U <- R U, W <- R W ->
+//   Gram-Schmidt reunitarisation -> store,
+// accumulating the change of sum_p beta_p Re Tr U_p / 3 and the counters.
+// The links of one slice are independent (Sec. 2), so one thread owns one
+// link and the slice is one launch.
+#include <hip/hip_cooperative_groups.h>
+
+#include "geometry.h"
+#include "kernels.h"
+
+namespace su3hb {
+
+// One SU(2)-subgroup heatbath on rows (I, J) of U (and W = U A).
+template <int I, int J, int SUB>
+__device__ __forceinline__ void su2_heatbath(mat3<double> &U, mat3<double> &W, uint32_t lid,
+                                             uint32_t sweep, int nhit, uint32_t k0, uint32_t k1,
+                                             int &attempts, int &accepts)
+{
+    // quaternion part a0 + i a.sigma of the 2x2 block (I, J) of W
+    const double a0 = 0.5 * (W.e[I][I].re + W.e[J][J].re);
+    const double a1 = 0.5 * (W.e[I][J].im + W.e[J][I].im);
+    const double a2 = 0.5 * (W.e[I][J].re - W.e[J][I].re);
+    const double a3 = 0.5 * (W.e[I][I].im - W.e[J][J].im);
+    const double k = sqrt(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))));
+    if (!(k > 1e-300)) return;  // degenerate projection: every hit rejected
+    const double alpha = 2.0 * k / 3.0;
+
+    // multi-hit Kennedy-Pendleton: delta = 1 - x0 ~ sqrt(delta) exp(-alpha delta),
+    // accepted with probability sqrt(1 - delta/2)
+    int hit = 0;
+    bool ok = false;
+    double delta = 0.0;
+    for (; hit < nhit; ++hit) {
+        const uint4 r = philox4x32_10(
+            make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1), kTagUpdate), k0, k1);
+        ++attempts;
+        const double c = cospi(2.0 * u01(r.y));  // cos(2 pi u)
+        delta = -(log(u01(r.x)) + c * c * log(u01(r.z))) / alpha;
+        const double r4 = u01(r.w);
+        if (r4 * r4 <= 1.0 - 0.5 * delta) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) return;
+    ++accepts;
+    const double x0 = 1.0 - delta;
+
+    // (x1, x2, x3) uniform on the sphere of radius sqrt(1 - x0^2)
+    const uint4 q = philox4x32_10(
+        make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1) | 1u, kTagUpdate), k0, k1);
+    const double rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
+    const double cth = 2.0 * u01(q.x) - 1.0;
+    const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+    double sph, cph;
+    sincospi(2.0 * u01(q.y), &sph, &cph);  // phi = 2 pi u
+    const double x1 = rad * sth * cph, x2 = rad * sth * sph, x3 = rad * cth;
+
+    // r = X V^dag, X = [[x0 + i x3, x2 + i x1], [-x2 + i x1, x0 - i x3]],
+    // V^dag = [[a0 - i a3, -a2 - i a1], [a2 - i a1, a0 + i a3]] / k
+    const double ik = 1.0 / k;
+    const cx<double> X00{x0, x3}, X01{x2, x1}, X10{-x2, x1}, X11{x0, -x3};
+    const cx<double> V00{a0 * ik, -a3 * ik}, V01{-a2 * ik, -a1 * ik}, V10{a2 * ik, -a1 * ik},
+        V11{a0 * ik, a3 * ik};
+    cx<double> r00{0, 0}, r01{0, 0}, r10{0, 0}, r11{0, 0};
+    cfma(r00, X00, V00); cfma(r00, X01, V10);
+    cfma(r01, X00, V01); cfma(r01, X01, V11);
+    cfma(r10, X10, V00); cfma(r10, X11, V10);
+    cfma(r11, X10, V01); cfma(r11, X11, V11);
+
+    // U <- R_IJ(r) U and W <- R_IJ(r) W (rows I and J)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<double> ui = U.e[I][c], uj = U.e[J][c];
+        cx<double> ni{0, 0}, nj{0, 0};
+        cfma(ni, r00, ui); cfma(ni, r01, uj);
+        cfma(nj, r10, ui); cfma(nj, r11, uj);
+        U.e[I][c] = ni;
+        U.e[J][c] = nj;
+        const cx<double> wi = W.e[I][c], wj = W.e[J][c];
+        cx<double> mi{0, 0}, mj{0, 0};
+        cfma(mi, r00, wi); cfma(mi, r01, wj);
+        cfma(mj, r10, wi); cfma(mj, r11, wj);
+        W.e[I][c] = mi;
+        W.e[J][c] = mj;
+    }
+}
+
+template <int D, int PREC>
+__device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &rep, uint32_t lt,
+                                            uint32_t sweep, int att[3], int acc[3], double &dtrace)
+{
+    using R = typename Store<PREC>::real;
+    const int p = a.parity, q = 1 - a.parity, mu = a.mu;
+    const uint32_t Vh = rep.Vh;
+    uint32_t layer = 0, h = lt;
+    if (h >= Vh) {
+        layer = 1;
+        h -= Vh;
+    }
+    Site<D> x;
+    x.from_half(rep, h, p, layer);
+    const uint32_t glued = rep.nlat == 2 ? rep.glued : 0u;
+    const double beta0 = a.use_rep_beta ? rep.beta0 : a.beta0;
+    const double beta1 = a.use_rep_beta ? rep.beta1 : a.beta1;
+
+    // staple sum A = sum_{nu != mu} beta_f U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+    //                             + beta_b U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+    const Step fm = step_fwd<D>(rep, x, mu, glued);
+    const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
+    mat3<R> A;
+    set_zero(A);
+#pragma unroll
+    for (int nu = 0; nu < D; ++nu) {
+        if (nu == mu) continue;
+        const Step fn = step_fwd<D>(rep, x, nu, glued);
+        const Step bn = step_bwd<D>(rep, x, nu, glued);
+        const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
+        const uint32_t s_mn = x.s + uint32_t(bn.ds), l_mn = layer ^ bn.flip;
+        const uint32_t s_pmmn = s_pm + uint32_t(bn.ds), l_pmmn = l_pm ^ bn.flip;
+
+        // forward staple: U_nu(x+mu) streamed by rows
+        {
+            const uint32_t tags = layer + l_pm + l_pn + layer;
+            const mat3<R> u2 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, l_pn, mu, q, s_pn), Vh);
+            const mat3<R> u3 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, layer, nu, p, x.s), Vh);
+            acc_forward_staple<PREC>(A, link_ptr<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), u2, u3, Vh,
+                                     R(tags == 0 ? beta0 : beta1));
+        }
+        // backward staple: U_mu(x-nu) and U_nu(x-nu) streamed by rows
+        {
+            const uint32_t tags = l_mn + l_pmmn + layer + l_mn;
+            const mat3<R> u2 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), Vh);
+            acc_backward_staple<PREC>(A, link_ptr<D, PREC>(a.links, rep, l_mn, mu, q, s_mn), u2,
+                                      link_ptr<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
+                                      R(tags == 0 ? beta0 : beta1));
+        }
+    }
+
+    auto *uptr = link_ptr<D, PREC>(a.links, rep, layer, mu, p, x.s);
+    mat3<double> U = widen<double>(load_link<PREC>(uptr, Vh));
+    mat3<double> W = mul_nn(U, widen<double>(A));   // A is not needed past this point
+    const double tr_old = W.e[0][0].re + W.e[1][1].re + W.e[2][2].re;
+
+    const uint32_t lid = ((rep.lat2test ? 0u : layer * rep.V) + x.s) * uint32_t(D) + uint32_t(mu);
+    su2_heatbath<0, 1, 0>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[0], acc[0]);
+    su2_heatbath<0, 2, 1>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[1], acc[1]);
+    su2_heatbath<1, 2, 2>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[2], acc[2]);
+    // W was rotated with U, so Re Tr W is now Re Tr(U' A)
+    dtrace += (W.e[0][0].re + W.e[1][1].re + W.e[2][2].re - tr_old) * (1.0 / 3.0);
+    reunitarize(U);
+    store_link<PREC>(uptr, Vh, U);
+}
+
+// Sum the per-thread counters over the block and add them to one slot.
+__device__ __forceinline__ void flush_stats(StatSlot *slots, uint32_t lb, int att[3], int acc[3], int upd,
+                                            double dtrace)
+{
+    int v[7] = {att[0], att[1], att[2], acc[0], acc[1], acc[2], upd};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], off);
+        dtrace += __shfl_xor(dtrace, off);
+    }
+    __shared__ int s_int[4][7];
+    __shared__ double s_dbl[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) s_int[wave][i] = v[i];
+        s_dbl[wave] = dtrace;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 1; w < nw; ++w) {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) v[i] += s_int[w][i];
+            dtrace += s_dbl[w];
+        }
+        StatSlot *sl = &slots[lb % kStatSlots];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            atomicAdd(&sl->attempts[i], (unsigned long long)v[i]);
+            atomicAdd(&sl->accepts[i], (unsigned long long)v[3 + i]);
+        }
+        atomicAdd(&sl->updates, (unsigned long long)v[6]);
+        unsafeAtomicAdd(&sl->dtrace, dtrace);
+    }
+    __syncthreads();  // the shared arrays are reused by the next block in a persistent loop
+}
+
+// Update the links of logical block lb (replica found by binary search).
+template <int D, int PREC>
+__device__ __forceinline__ void process_block(const UpdateArgs &a, uint32_t lb, uint32_t sweep)
+{
+    int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
+    double dtrace = 0.0;
+    if (lb < a.total_blocks) {
+        const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, false);
+        const RepDesc &rep = a.reps[r];
+        const uint32_t lt = (lb - rep.upd_block0) * blockDim.x + threadIdx.x;
+        if (lt < rep.nlat * rep.Vh) {
+            update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace);
+            upd = 1;
+        }
+    }
+    flush_stats(a.stats, lb, att, acc, upd, dtrace);
+}
+
+template <int D, int PREC>
+__global__ void __launch_bounds__(256) update_kernel(UpdateArgs a)
+{
+    uint32_t lb = blockIdx.x;
+    if (a.xcd_remap) {
+        // consecutive hardware blocks go round-robin over the 8 XCDs; give each
+        // XCD a contiguous run of logical blocks so neighbours share its L2
+        const uint32_t per = gridDim.x >> 3;
+        lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    }
+    process_block<D, PREC>(a, lb, *a.sweep);
+}
+
+// Persistent form for batches: the grid stays resident for n_sweeps sweeps,
+// loops over the logical blocks of every slice and meets at a grid barrier
+// between slices (the next slice reads links this one wrote).  The sweep
+// number is the counter's value at entry plus the local sweep index; the
+// counter itself is advanced once, by the host, after the launch.
+template <int D, int PREC>
+__global__ void __launch_bounds__(256) update_persistent_kernel(UpdateArgs a, int n_sweeps)
+{
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const uint32_t sweep0 = *a.sweep;
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        for (int p = 0; p < 2; ++p) {
+            for (int mu = 0; mu < D; ++mu) {
+                UpdateArgs b = a;
+                b.parity = p;
+                b.mu = mu;
+                for (uint32_t lb = blockIdx.x; lb < a.total_blocks; lb += gridDim.x)
+                    process_block<D, PREC>(b, lb, sweep0 + uint32_t(sw));
+                grid.sync();
+            }
+        }
+    }
+}
+
+template <int D, int PREC>
+static hipError_t launch_update_t(dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
+{
+    hipLaunchKernelGGL((update_kernel<D, PREC>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_update_d(int prec, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
+{
+    switch (prec) {
+    case kFP64_18: return launch_update_t<D, kFP64_18>(grid, block, st, a);
+    case kFP32_18: return launch_update_t<D, kFP32_18>(grid, block, st, a);
+    case kFP32_12: return launch_update_t<D, kFP32_12>(grid, block, st, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D, int PREC>
+static const void *persistent_fn()
+{
+    return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC>);
+}
+
+static const void *persistent_fn(int D, int prec)
+{
+#define SU3HB_P(DD)                                                   \
+    case DD:                                                          \
+        switch (prec) {                                               \
+        case kFP64_18: return persistent_fn<DD, kFP64_18>();          \
+        case kFP32_18: return persistent_fn<DD, kFP32_18>();          \
+        case kFP32_12: return persistent_fn<DD, kFP32_12>();          \
+        default: return nullptr;                                      \
+        }
+    switch (D) {
+        SU3HB_P(2)
+        SU3HB_P(3)
+        SU3HB_P(4)
+        SU3HB_P(5)
+        SU3HB_P(6)
+    default: return nullptr;
+    }
+#undef SU3HB_P
+}
+
+hipError_t persistent_max_blocks(int D, int prec, int threads, int *blocks_per_cu)
+{
+    const void *fn = persistent_fn(D, prec);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, 0);
+}
+
+hipError_t launch_update_persistent(int D, int prec, int blocks, int threads, hipStream_t st,
+                                    const UpdateArgs &a, int n_sweeps)
+{
+    const void *fn = persistent_fn(D, prec);
+    if (!fn) return hipErrorInvalidValue;
+    UpdateArgs args = a;
+    int ns = n_sweeps;
+    void *params[] = {&args, &ns};
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), params, 0, st);
+}
+
+hipError_t launch_update(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
+{
+    switch (D) {
+    case 2: return launch_update_d<2>(prec, grid, block, st, a);
+    case 3: return launch_update_d<3>(prec, grid, block, st, a);
+    case 4: return launch_update_d<4>(prec, grid, block, st, a);
+    case 5: return launch_update_d<5>(prec, grid, block, st, a);
+    case 6: return launch_update_d<6>(prec, grid, block, st, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace su3hb

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every function include/su3hb.h declares,
+and rejects bad arguments before touching the GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_0904_0642_amd as su3hb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "su3hb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(su3hb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_calls():
+    names = declared_functions()
+    for required in ("su3hb_init_lattice", "su3hb_sweep", "su3hb_plaquette", "su3hb_get_links",
+                     "su3hb_set_links", "su3hb_free", "su3hb_last_error", "su3hb_batch_create",
+                     "su3hb_autotune"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(su3hb.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing
+    # and the binding marshals every one of them
+    assert sorted(su3hb.exported_names()) == declared_functions()
+
+
+def test_links_bytes():
+    for prec, b in ((su3hb.FP64_18, 144), (su3hb.FP32_18, 72), (su3hb.FP32_12, 48)):
+        p = su3hb.make_params([4, 4, 4, 4], precision=prec)
+        assert su3hb.su3hb_links_bytes(p) == 256 * 4 * b
+    p = su3hb.make_params([24, 24, 24, 8], nlat=2, dlt_mask=15, precision=su3hb.FP32_18)
+    assert su3hb.su3hb_links_bytes(p) == 2 * 24 ** 3 * 8 * 4 * 72
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(extents=[3, 4, 4, 4]), "even"),
+    (dict(extents=[4]), "nd"),
+    (dict(extents=[4] * 7), "nd"),
+    (dict(extents=[4, 4], nlat=3), "nlat"),
+    (dict(extents=[4, 4], dlt_mask=1), "nlat = 2"),
+    (dict(extents=[4, 4], lat2test=True), "nlat = 2"),
+    (dict(extents=[4, 4], nlat=2, dlt_mask=4), "dlt_mask"),
+    (dict(extents=[4, 4], precision=7), "precision"),
+    (dict(extents=[4, 4], start=9), "start"),
+    (dict(extents=[0, 4]), "even"),
+])
+def test_init_rejects_bad_parameters(kw, frag):
+    ext = kw.pop("extents")
+    p = su3hb.make_params(ext, **kw)
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        su3hb.su3hb_init_lattice(p)
+    assert ei.value.code == su3hb.EINVAL
+    assert frag in str(ei.value)
+
+
+def test_null_handles_are_rejected():
+    lib = su3hb.lib()
+    assert lib.su3hb_sweep(None, 6.0, 6.0, 8, 1, None) == su3hb.EINVAL
+    assert lib.su3hb_plaquette(None, 6.0, 6.0, None) == su3hb.EINVAL
+    assert lib.su3hb_get_links(None, None, 0) == su3hb.EINVAL
+    assert lib.su3hb_batch_sweep(None, 8, 1, 0, None) == su3hb.EINVAL
+    assert "NULL" in su3hb.last_error() or "batch" in su3hb.last_error()
+    lib.su3hb_free(None)
+    lib.su3hb_batch_free(None)
+
+
+def test_batch_rejects_bad_replicas():
+    with pytest.raises(su3hb.SU3HBError):
+        su3hb.su3hb_batch_create(4, [((4, 4, 4, 3), 6.0, 1, su3hb.HOT)], su3hb.FP32_18)
+    with pytest.raises(su3hb.SU3HBError):
+        su3hb.su3hb_batch_create(4, [], su3hb.FP32_18)
+
+
+def test_no_cpu_fallback_in_package():
+    # the product path never imports the oracle
+    pkg = os.path.join(ROOT, "paper_0904_0642_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt and "liboracle" not in txt

@@ -1,0 +1,267 @@
+"""GPU <-> oracle parity through the C ABI.
+
+Both sides draw the same Philox random numbers, so after one sweep from a
+shared start every link must agree to rounding:
+  * FP64 storage: max |U_gpu - U_oracle| <= 1e-10 per matrix element
+    (the bound the build targets; libm vs device log/cos/sqrt differ by ulps);
+  * FP32 storage: <= 1e-4 (FP32 staple products; the error is printed).
+Cases span several blocks with ragged tails, D = 2..6, the double-layered
+torus (beta0 != beta1), lat2test, and the edge cases of the interface.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_0904_0642_amd as su3hb
+from paper_0904_0642_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    su3hb.lib()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(oracle_mod, ext, nlat=1, mask=0, lat2test=False, prec=su3hb.FP64_18, start=su3hb.HOT, seed=1,
+         threads=8):
+    say(f"case ext={ext} nlat={nlat} mask={mask} lat2test={lat2test} prec={prec} start={start} seed={seed}")
+    g = su3hb.Lattice(ext, nlat=nlat, dlt_mask=mask, lat2test=lat2test, precision=prec, start=start, seed=seed)
+    o = oracle_mod.Lattice(ext, nlat=nlat, dlt_mask=mask, lat2test=lat2test, seed=seed, threads=threads)
+    if start == su3hb.COLD:
+        o.cold_start()
+    else:
+        o.hot_start()
+    return g, o
+
+
+def maxdiff(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max())
+
+
+# ---------------------------------------------------------------------------
+
+def test_config1_cold_4x4x4x4(oracle_mod):
+    # 4^4, beta = 6.0, ordered start, n_hit = 8, seed 1, 20 sweeps, FP64
+    g, o = pair(oracle_mod, [4, 4, 4, 4], start=su3hb.COLD, seed=1)
+    assert maxdiff(g.get_links(), o.get_links()) == 0.0
+    st_g = g.sweep(6.0, n_hit=8, n_sweeps=1, stats=True)
+    st_o = o.sweep(6.0, nhit=8, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  after 1 sweep: max |dU| = {d:.3e}")
+    assert d <= TOL64
+    assert list(st_g["attempts"]) == list(st_o["attempts"])
+    assert list(st_g["accepts"]) == list(st_o["accepts"])
+    assert st_g["link_updates"] == 1024
+    assert abs(st_g["dtrace"] - st_o["dtrace"]) < 1e-9
+    # per-sweep plaquette over the remaining 19 sweeps
+    series = g.sweep_measure(6.0, n_hit=8, n_sweeps=19)
+    ref = []
+    for _ in range(19):
+        o.sweep(6.0, nhit=8, nsweeps=1)
+        ref.append(o.plaquette(6.0))
+    ref = np.array(ref)
+    dp = np.abs(series[:, :4] - ref[:, :4]).max(axis=1)
+    say(f"  per-sweep |d<P>| max over 19 sweeps = {dp.max():.3e}; first = {dp[0]:.3e}")
+    assert dp.max() < 1e-8
+    assert g.get_state() == (1, 20)
+
+
+@pytest.mark.parametrize("ext,seed", [([4, 4, 4, 4], 1), ([6, 4, 2, 10], 3), ([16, 16, 16, 16], 1)])
+def test_hot_start_matches(oracle_mod, ext, seed):
+    g, o = pair(oracle_mod, ext, seed=seed)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  hot start max |dU| = {d:.3e}")
+    assert d <= 1e-12
+
+
+@pytest.mark.parametrize("beta", [5.7, 6.0])
+def test_16x16x16x16_one_sweep(oracle_mod, beta):
+    g, o = pair(oracle_mod, [16, 16, 16, 16], seed=1, threads=16)
+    g.sweep(beta, n_hit=8, n_sweeps=1)
+    o.sweep(beta, nhit=8, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  16^4 beta={beta}: max |dU| = {d:.3e}")
+    assert d <= TOL64
+    pg = g.plaquette(beta)
+    po = o.plaquette(beta)
+    assert np.allclose(pg[[0, 1, 2, 3, 5]], po[[0, 1, 2, 3, 5]], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("ext", [[32, 32], [4, 6], [6, 4, 8], [4, 4, 2, 4, 2], [2, 4, 2, 2, 2, 4],
+                                 [2, 2, 2, 2], [10, 2, 6, 4]])
+def test_dimensions_and_ragged(oracle_mod, ext):
+    g, o = pair(oracle_mod, ext, seed=5)
+    for _ in range(2):
+        g.sweep(5.8, n_hit=4, n_sweeps=1)
+        o.sweep(5.8, nhit=4, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  {ext}: max |dU| after 2 sweeps = {d:.3e}")
+    assert d <= TOL64
+    pg, po = g.plaquette(5.8), o.plaquette(5.8)
+    good = ~np.isnan(po)
+    assert np.array_equal(np.isnan(pg), np.isnan(po))
+    assert np.allclose(pg[good], po[good], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("mask,b0,b1", [(0b1111, 5.5, 6.0), (0b0111, 5.65, 5.9), (0b0000, 5.6, 6.1),
+                                        (0b1000, 6.0, 6.0)])
+def test_double_layered_torus(oracle_mod, mask, b0, b1):
+    g, o = pair(oracle_mod, [4, 6, 4, 2], nlat=2, mask=mask, seed=9)
+    st_g = g.sweep(b0, b1, n_hit=8, n_sweeps=2, stats=True)
+    st_o = o.sweep(b0, b1, nhit=8, nsweeps=2)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  DLT mask={mask:04b} beta=({b0},{b1}): max |dU| = {d:.3e}")
+    assert d <= TOL64
+    assert abs(st_g["dtrace"] - st_o["dtrace"]) < 1e-9 * max(1.0, abs(st_o["dtrace"]))
+    pg, po = g.plaquette(b0, b1), o.plaquette(b0, b1)
+    assert np.allclose(pg, po, rtol=1e-12, atol=0, equal_nan=True)
+
+
+def test_lat2test_layers_equal_torus(oracle_mod):
+    ext = [4, 4, 2, 4]
+    t = su3hb.Lattice(ext, nlat=2, dlt_mask=0b1111, lat2test=True, seed=44)
+    p = su3hb.Lattice(ext, seed=44)
+    t.sweep(5.65, n_hit=8, n_sweeps=3)
+    p.sweep(5.65, n_hit=8, n_sweeps=3)
+    lt, lp = t.get_links(), p.get_links()
+    assert np.array_equal(lt[0], lp[0]) and np.array_equal(lt[1], lp[0])
+
+
+@pytest.mark.parametrize("prec", [su3hb.FP32_18, su3hb.FP32_12])
+def test_fp32_storage_one_sweep(oracle_mod, prec):
+    # shared start: the oracle takes the FP32-rounded links the GPU holds
+    g, o = pair(oracle_mod, [8, 8, 8, 4], prec=prec, seed=2)
+    start = g.get_links()
+    o.set_links(start)
+    g.sweep(6.0, n_hit=8, n_sweeps=1)
+    o.sweep(6.0, nhit=8, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  prec={prec}: max |dU| after 1 sweep = {d:.3e}")
+    assert d <= TOL32
+    # links stay in SU(3) to FP32 rounding
+    u = g.get_links().reshape(-1, 3, 3)
+    unit = np.abs(np.einsum("nij,nkj->nik", u, u.conj()) - np.eye(3)).max()
+    assert unit < 1e-6
+
+
+def test_plaquette_of_same_links(oracle_mod):
+    g, o = pair(oracle_mod, [8, 4, 6, 4], seed=13)
+    o.sweep(5.9, nhit=2, nsweeps=1)
+    g.set_links(o.get_links())
+    assert np.allclose(g.plaquette(5.9), o.plaquette(5.9), rtol=1e-13, atol=0, equal_nan=True)
+
+
+def test_set_links_rejects_non_su3(oracle_mod):
+    g = su3hb.Lattice([4, 4, 2, 2], seed=3)
+    good = g.get_links()
+    bad = good.copy()
+    bad[0, 5, 1] *= 1.001
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        g.set_links(bad)
+    assert ei.value.code == su3hb.ENOTSU3
+    nan = good.copy()
+    nan[0, 7, 0, 1, 1] = np.nan
+    with pytest.raises(su3hb.SU3HBError):
+        g.set_links(nan)
+    assert np.array_equal(g.get_links(), good)            # unchanged after a failed set
+    with pytest.raises(su3hb.SU3HBError):
+        su3hb.su3hb_set_links(g.handle, good.view(np.float64).reshape(-1)[:-18])
+    g.set_links(good)
+    assert np.array_equal(g.get_links(), good)
+
+
+def test_sweep_argument_errors():
+    g = su3hb.Lattice([4, 4, 2, 2], seed=3)
+    for bad in (dict(n_hit=0), dict(n_hit=40000), dict(n_sweeps=-1)):
+        kw = dict(n_hit=8, n_sweeps=1)
+        kw.update(bad)
+        with pytest.raises(su3hb.SU3HBError) as ei:
+            g.sweep(6.0, **kw)
+        assert ei.value.code == su3hb.EINVAL
+    with pytest.raises(su3hb.SU3HBError):
+        g.sweep(float("nan"))
+    g.sweep(6.0, n_sweeps=0)
+    assert g.get_state()[1] == 0
+
+
+def test_resume_is_bitwise(oracle_mod):
+    a = su3hb.Lattice([8, 4, 4, 4], seed=21)
+    a.sweep(5.8, n_hit=8, n_sweeps=6)
+    b = su3hb.Lattice([8, 4, 4, 4], seed=21)
+    b.sweep(5.8, n_hit=8, n_sweeps=2)
+    links, (seed, sw) = b.get_links(), b.get_state()
+    c = su3hb.Lattice([8, 4, 4, 4], seed=999, start=su3hb.COLD)
+    c.set_links(links)
+    c.set_state(seed, sw)
+    c.sweep(5.8, n_hit=8, n_sweeps=4)
+    assert np.array_equal(a.get_links(), c.get_links())
+    assert c.get_state() == (21, 6)
+
+
+@pytest.mark.parametrize("prec", [su3hb.FP64_18, su3hb.FP32_12])
+def test_launch_shape_invariance(prec):
+    ref = None
+    for block in (64, 128, 256):
+        for xcd in (0, 1):
+            g = su3hb.Lattice([12, 6, 4, 4], seed=8, precision=prec)
+            g.set_launch(block, xcd)
+            assert g.get_launch() == (block, xcd)
+            g.sweep(6.1, n_hit=8, n_sweeps=2)
+            links = g.get_links()
+            if ref is None:
+                ref = links
+            assert np.array_equal(links, ref), (block, xcd)
+
+
+def test_graph_replay_equals_direct_launches():
+    # graph replays (su3hb_sweep) against kernel-by-kernel launches
+    # (su3hb_sweep_timed), with eager work and synchronisation in between
+    a = su3hb.Lattice([8, 8, 4, 4], seed=31)
+    b = su3hb.Lattice([8, 8, 4, 4], seed=31)
+    for k in range(4):
+        sa = a.sweep_measure(5.9, n_hit=8, n_sweeps=2)
+        _, sb = b.sweep_timed(5.9, n_hit=8, n_sweeps=2, measure=True)
+        assert np.array_equal(a.get_links(), b.get_links()), k
+        assert np.array_equal(sa, sb, equal_nan=True), k
+        a.plaquette(5.9)
+    assert a.get_state() == b.get_state() == (31, 8)
+
+
+def test_running_trace_matches_recompute():
+    g = su3hb.Lattice([8, 8, 8, 4], seed=4)
+    t0 = g.plaquette(5.7)[5]
+    st = g.sweep(5.7, n_hit=8, n_sweeps=10, stats=True)
+    t1 = g.plaquette(5.7)[5]
+    say(f"  running trace {t0 + st['dtrace']:.12f} vs recomputed {t1:.12f}")
+    assert abs(t0 + st["dtrace"] - t1) < 1e-11 * abs(t1)
+    assert st["link_updates"] == 10 * 2048 * 4
+
+
+@pytest.mark.parametrize("prec", [su3hb.FP64_18, su3hb.FP32_18])
+def test_batch_replica_equals_single(prec):
+    reps = [((8, 8, 8, 8), 5.7, 101, su3hb.HOT), ((6, 4, 4, 2), 6.3, 202, su3hb.HOT),
+            ((4, 4, 4, 4), 5.5, 303, su3hb.COLD)]
+    b0 = su3hb.Batch(4, reps, precision=prec)
+    b1 = su3hb.Batch(4, reps, precision=prec)
+    b0.sweep(n_hit=8, n_sweeps=3, mode=0)
+    b1.sweep(n_hit=8, n_sweeps=3, mode=1)      # persistent cooperative launch
+    pb = b0.plaquette()
+    for r, (ext, beta, seed, start) in enumerate(reps):
+        s = su3hb.Lattice(ext, precision=prec, start=start, seed=seed)
+        s.sweep(beta, n_hit=8, n_sweeps=3)
+        ls = s.get_links()
+        assert np.array_equal(b0.get_links(r), ls), r
+        assert np.array_equal(b1.get_links(r), ls), r
+        assert np.allclose(pb[r], s.plaquette(beta), rtol=1e-14, atol=0, equal_nan=True)
