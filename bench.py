@@ -76,7 +76,7 @@ def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int):
     lat = su3hb.Lattice(ext, precision=prec, start=su3hb.HOT, seed=1)
     if autotune_ms > 0:
         lat.autotune(autotune_ms)
-    block, xcd = lat.get_launch()
+    block, order, waves = lat.get_launch()
     if warmup > 0:
         lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=warmup)
     torch.cuda.synchronize()
@@ -102,7 +102,7 @@ def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int):
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel": f"update_kernel<{D},{PREC_NAME[prec]}>"},
         "plaquette_first_last": [float(plaq[0]), float(plaq[-1])],
-        "launch": {"block": block, "xcd_remap": xcd},
+        "launch": {"block": block, "order": order, "waves": waves},
         "extents": list(ext), "precision": PREC_NAME[prec], "beta": beta, "links_per_sweep": links_per_sweep,
     }
     lat.close()

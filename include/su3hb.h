@@ -153,11 +153,16 @@ int su3hb_set_links(su3hb_lattice *lat, const double *host, size_t n);
 int su3hb_get_state(const su3hb_lattice *lat, uint64_t *seed, uint64_t *sweep);
 int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
 
-/* Launch shape of the update kernel: threads per block (64, 128 or 256) and
- * whether blocks are renumbered so that each XCD works on a contiguous part
- * of the lattice.  Results are bit-identical for every shape. */
-int su3hb_set_launch(su3hb_lattice *lat, int block, int xcd_remap);
-int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *xcd_remap);
+/* Launch shape of the update kernel.  block: threads per block (64, 128 or
+ * 256).  order: 0 = hardware block order; 1 = each XCD gets a contiguous run
+ * of blocks; 2 = each of the 8 XCDs gets a slab of the last direction and
+ * walks it with that direction fastest (applies to one single-layer lattice
+ * whose last extent is a multiple of 8 and whose blocks tile an
+ * (x_{D-2}, x_{D-1}) plane; elsewhere it acts as 1).  waves: minimum waves
+ * per SIMD the kernel is compiled for, 2, or 3 (D = 4 only).  Results are
+ * bit-identical for every shape.  get_launch reports the order in effect. */
+int su3hb_set_launch(su3hb_lattice *lat, int block, int order, int waves);
+int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *order, int *waves);
 
 /* Time the candidate launch shapes on this lattice for about budget_ms and
  * keep the fastest (cached per precision, D and extents for the process).

@@ -64,8 +64,8 @@ _SIGS = {
     "su3hb_set_links": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_size_t]),
     "su3hb_get_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "su3hb_set_state": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64]),
-    "su3hb_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
-    "su3hb_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "su3hb_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "su3hb_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "su3hb_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "su3hb_sweep_timed": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -194,14 +194,14 @@ def su3hb_set_state(h, seed, sweep):
     _check(lib().su3hb_set_state(h, int(seed) & (2**64 - 1), int(sweep)))
 
 
-def su3hb_set_launch(h, block, xcd_remap):
-    _check(lib().su3hb_set_launch(h, int(block), int(xcd_remap)))
+def su3hb_set_launch(h, block, order, waves=2):
+    _check(lib().su3hb_set_launch(h, int(block), int(order), int(waves)))
 
 
 def su3hb_get_launch(h):
-    b, x = C.c_int(), C.c_int()
-    _check(lib().su3hb_get_launch(h, C.byref(b), C.byref(x)))
-    return b.value, x.value
+    b, o, w = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().su3hb_get_launch(h, C.byref(b), C.byref(o), C.byref(w)))
+    return b.value, o.value, w.value
 
 
 def su3hb_autotune(h, budget_ms=200):
@@ -331,8 +331,8 @@ class Lattice:
     def set_state(self, seed, sweep):
         su3hb_set_state(self._h, seed, sweep)
 
-    def set_launch(self, block, xcd_remap):
-        su3hb_set_launch(self._h, block, xcd_remap)
+    def set_launch(self, block, order, waves=2):
+        su3hb_set_launch(self._h, block, order, waves)
 
     def get_launch(self):
         return su3hb_get_launch(self._h)
@@ -382,8 +382,8 @@ class Batch:
         a = np.ascontiguousarray(np.asarray(links, dtype=np.complex128)).view(np.float64).reshape(-1)
         su3hb_batch_set_links(self._h, r, a)
 
-    def set_launch(self, block, xcd_remap):
-        su3hb_set_launch(self._h, block, xcd_remap)
+    def set_launch(self, block, order, waves=2):
+        su3hb_set_launch(self._h, block, order, waves)
 
     def autotune(self, budget_ms=200):
         su3hb_autotune(self._h, budget_ms)

@@ -51,11 +51,11 @@ __device__ __forceinline__ void load_row(const typename Store<PREC>::elem *__res
     }
 }
 
-// Each thread handles `spt` sites of its block's range; per site the
-// D(D-1)/2 plaquettes based at x,
+// One thread per site (`spt` sites per thread, strided by the block size):
+// the D(D-1)/2 plaquettes based at x,
 // (1/3) Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = (1/3) Re Tr(T1 T2^dag)
-// with T1 = U_mu(x) U_nu(x+mu), T2 = U_nu(x) U_mu(x+nu), all in FP64.  T1 and
-// T2 are formed row by row so only the two neighbour links are held whole.
+// with T1 = U_mu(x) U_nu(x+mu), T2 = U_nu(x) U_mu(x+nu); products in FP64.
+// All planes of a site are unrolled so their loads are in flight together.
 // Partial sums per block: [spacelike, timelike, layer0, layer1, beta-weighted].
 template <int D, int PREC>
 __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
@@ -82,47 +82,27 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
             x.from_half(rep, h, p, layer);
             const int q = 1 - p;
             double site_sum = 0.0;
-#pragma unroll 1
-            for (int pl = 0; pl < D * (D - 1) / 2; ++pl) {
-                // plane index -> (mu, nu), mu < nu
-                int mu = 0, nu = 1, k = pl;
-                while (k >= D - 1 - mu) {
-                    k -= D - 1 - mu;
-                    ++mu;
-                }
-                nu = mu + 1 + k;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) {
                 const Step fm = step_fwd<D>(rep, x, mu, glued);
-                const Step fn = step_fwd<D>(rep, x, nu, glued);
                 const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
-                const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
-                const mat3<double> b = widen<double>(
-                    load_link<PREC>(link_ptr<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh));
-                const mat3<double> c = widen<double>(
-                    load_link<PREC>(link_ptr<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh));
-                const auto *pu = link_ptr<D, PREC>(links, rep, layer, mu, p, x.s);
-                const auto *pv = link_ptr<D, PREC>(links, rep, layer, nu, p, x.s);
-                double tr = 0.0;
+                const mat3<double> umx = widen<double>(
+                    load_link<PREC>(link_ptr<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh));
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    cx<double> ur[3], vr[3];
-                    load_row<PREC>(pu, rep.Vh, i, ur);
-                    load_row<PREC>(pv, rep.Vh, i, vr);
-#pragma unroll
-                    for (int jj = 0; jj < 3; ++jj) {
-                        cx<double> t1{0.0, 0.0}, t2{0.0, 0.0};
-#pragma unroll
-                        for (int kk = 0; kk < 3; ++kk) {
-                            cfma(t1, ur[kk], b.e[kk][jj]);
-                            cfma(t2, vr[kk], c.e[kk][jj]);
-                        }
-                        tr = fma(t1.re, t2.re, fma(t1.im, t2.im, tr));
-                    }
+                for (int nu = mu + 1; nu < D; ++nu) {
+                    const Step fn = step_fwd<D>(rep, x, nu, glued);
+                    const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
+                    const mat3<double> t1 = mul_nn(
+                        umx, widen<double>(load_link<PREC>(link_ptr<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh)));
+                    const mat3<double> t2 = mul_nn(
+                        widen<double>(load_link<PREC>(link_ptr<D, PREC>(links, rep, layer, nu, p, x.s), rep.Vh)),
+                        widen<double>(load_link<PREC>(link_ptr<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh)));
+                    const double P = re_tr_na(t1, t2) * (1.0 / 3.0);
+                    if (nu == D - 1) v[1] += P; else v[0] += P;
+                    site_sum += P;
+                    const uint32_t tags = layer + l_pm + l_pn + layer;
+                    v[4] += (tags == 0 ? beta0 : beta1) * P;
                 }
-                const double P = tr * (1.0 / 3.0);
-                if (nu == D - 1) v[1] += P; else v[0] += P;
-                site_sum += P;
-                const uint32_t tags = layer + l_pm + l_pn + layer;
-                v[4] += (tags == 0 ? beta0 : beta1) * P;
             }
             if (layer == 0) v[2] += site_sum; else v[3] += site_sum;
         }
@@ -131,6 +111,61 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
     if (threadIdx.x == 0 && lb < a.total_blocks)
 #pragma unroll
         for (int i = 0; i < 5; ++i) a.partials[size_t(lb) * 5 + i] = v[i];
+}
+
+// Fused measurement of a single-layer lattice: meas[mu][b] holds the block
+// sums of (1/3) Re Tr U_p over the planes (nu, mu), nu < mu, written by the
+// parity-1 update slices.  One block adds them up in a fixed order.
+__global__ void __launch_bounds__(1024) measure_finalize_kernel(const double *meas, int D, uint32_t nblocks,
+                                                                 double V, double beta0, double *out,
+                                                                 double *series, uint32_t *cursor)
+{
+    double v[2] = {0.0, 0.0};  // spacelike, timelike
+    for (int mu = 1; mu < D; ++mu) {
+        double s = 0.0;
+        for (uint32_t b = threadIdx.x; b < nblocks; b += blockDim.x) s += meas[size_t(mu) * nblocks + b];
+        v[mu == D - 1 ? 1 : 0] += s;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        v[0] += __shfl_xor(v[0], off);
+        v[1] += __shfl_xor(v[1], off);
+    }
+    __shared__ double sh[16][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[wave][0] = v[0];
+        sh[wave][1] = v[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) {
+            v[0] += sh[w][0];
+            v[1] += sh[w][1];
+        }
+        const double nspace = V * (D - 1) * (D - 2) / 2.0, ntime = V * (D - 1);
+        const double nan = __builtin_nan("");
+        double o[6];
+        o[0] = (v[0] + v[1]) / (nspace + ntime);
+        o[1] = nspace > 0 ? v[0] / nspace : nan;
+        o[2] = v[1] / ntime;
+        o[3] = o[0];
+        o[4] = nan;
+        o[5] = beta0 * (v[0] + v[1]);
+        for (int i = 0; i < 6; ++i) out[i] = o[i];
+        if (series) {
+            const uint32_t k = atomicAdd(cursor, 1u);
+            for (int i = 0; i < 6; ++i) series[size_t(k) * 6 + i] = o[i];
+        }
+    }
+}
+
+hipError_t launch_measure_finalize(hipStream_t st, const double *meas, int D, uint32_t nblocks, double V,
+                                   double beta0, double *out, double *series, uint32_t *cursor)
+{
+    hipLaunchKernelGGL(measure_finalize_kernel, dim3(1), dim3(1024), 0, st, meas, D, nblocks, V, beta0, out,
+                       series, cursor);
+    return hipGetLastError();
 }
 
 // One block per replica: fixed-order sum of its block partials, normalised.

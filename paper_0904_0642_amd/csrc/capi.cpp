@@ -74,12 +74,14 @@ struct su3hb_lattice {
     StatSlot *d_stats = nullptr;
     StatSlot *d_stats_out = nullptr;
     double *d_partials = nullptr;
+    double *d_meas = nullptr;     // fused measurement partials, [D][update blocks]
+    size_t meas_cap = 0;
     double *d_plaq = nullptr;
     double *d_series = nullptr;
     uint32_t *d_cursor = nullptr;
     unsigned long long *d_maxdef = nullptr;
     double *d_stage = nullptr;
-    int block = 256, xcd = 1;
+    int block = 256, order = 1, waves = kDefaultWaves;
     uint32_t upd_blocks = 0, plq_blocks = 0;
     bool use_graph = true;
     GraphCache graph;
@@ -90,7 +92,10 @@ struct su3hb_lattice {
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;
+struct Shape {
+    int block, order, waves;
+};
+std::map<std::string, Shape> g_tune_cache;
 
 void drop_graph(su3hb_lattice *L)
 {
@@ -111,10 +116,10 @@ void layout_reps(su3hb_lattice *L)
         r.upd_block0 = ub;
         r.upd_blocks = (r.nlat * r.Vh + L->block - 1) / L->block;
         ub += r.upd_blocks;
-        // a few sites per plaquette thread keeps the partial sums to about
-        // 2048 blocks per lattice, which the finalize pass adds up quickly
+        // a few sites per plaquette thread keep the partial sums to about 4096
+        // blocks per lattice for the finalize pass
         const uint32_t nsite = r.nlat * r.V;
-        r.plq_spt = std::min<uint32_t>(16, std::max<uint32_t>(1, nsite / (uint32_t(kPlaqBlock) * 2048u)));
+        r.plq_spt = std::min<uint32_t>(16, std::max<uint32_t>(1, nsite / (uint32_t(kPlaqBlock) * 4096u)));
         r.plq_block0 = pb;
         r.plq_blocks = (nsite + kPlaqBlock * r.plq_spt - 1) / (kPlaqBlock * r.plq_spt);
         pb += r.plq_blocks;
@@ -230,6 +235,7 @@ void destroy(su3hb_lattice *L)
     hipFree(L->d_stats);
     hipFree(L->d_stats_out);
     hipFree(L->d_partials);
+    hipFree(L->d_meas);
     hipFree(L->d_plaq);
     hipFree(L->d_series);
     hipFree(L->d_cursor);
@@ -248,6 +254,25 @@ int start_replica(su3hb_lattice *L, int r, int mode)
     return SU3HB_OK;
 }
 
+// Order 2 (XCD slabs of the last direction) needs one single-layer lattice,
+// a last extent divisible by 8 and blocks that tile an (x_{D-2}, x_{D-1}) plane.
+bool slab_order_ok(const su3hb_lattice *L, int block)
+{
+    if (L->batch || L->nrep != 1 || L->nd < 3) return false;
+    const RepDesc &r = L->reps[0];
+    if (r.nlat != 1) return false;
+    const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
+    if (nl % 8) return false;
+    const uint32_t plane = r.Vh / (nl * n2);
+    return plane % uint32_t(block) == 0;
+}
+
+int effective_order(const su3hb_lattice *L)
+{
+    if (L->order == 2 && !slab_order_ok(L, L->block)) return 1;
+    return L->order;
+}
+
 UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
 {
     UpdateArgs a;
@@ -257,7 +282,14 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
     a.nrep = L->nrep;
     a.nhit = nhit;
     a.use_rep_beta = L->batch ? 1 : 0;
-    a.xcd_remap = L->xcd;
+    a.order = effective_order(L);
+    if (a.order == 2) {
+        const RepDesc &r = L->reps[0];
+        const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
+        a.slab = nl / 8;
+        a.cp = r.Vh / (nl * n2) / uint32_t(L->block);
+        a.n2 = n2;
+    }
     a.beta0 = b0;
     a.beta1 = b1;
     a.sweep = L->d_sweep;
@@ -269,7 +301,7 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
 dim3 update_grid(const su3hb_lattice *L)
 {
     uint32_t g = L->upd_blocks;
-    if (L->xcd) g = (g + 7) / 8 * 8;
+    if (effective_order(L) == 1) g = (g + 7) / 8 * 8;
     return dim3(g);
 }
 
@@ -291,19 +323,75 @@ int enqueue_plaquette(su3hb_lattice *L, hipStream_t st, double b0, double b1, do
     return SU3HB_OK;
 }
 
-// One sweep: parity 0 then 1, directions 0..D-1 inside, then the counter.
-int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nhit, int measure)
+// The plaquettes of a single-layer lattice are measured inside the parity-1
+// update slices (see update.hip); two layers and batches use the plaquette
+// kernel after the sweep.
+bool fused_measure(const su3hb_lattice *L) { return !L->batch && L->reps[0].nlat == 1; }
+
+int ensure_meas(su3hb_lattice *L)
+{
+    const size_t need = size_t(L->nd) * L->upd_blocks;
+    if (need <= L->meas_cap) return SU3HB_OK;
+    hipFree(L->d_meas);
+    L->d_meas = nullptr;
+    L->meas_cap = 0;
+    hipError_t e = hipMalloc(&L->d_meas, sizeof(double) * need);
+    if (e != hipSuccess) return fail(SU3HB_ENOMEM, "measurement buffer: %s", hipGetErrorString(e));
+    L->meas_cap = need;
+    return SU3HB_OK;
+}
+
+// One sweep: parity 0 then 1, directions 0..D-1 inside, then the counter and
+// (measure != 0) the plaquettes into the series.  `timed` (optional) records
+// an event pair around every update launch and the plaquette launch.
+int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nhit, int measure,
+                  std::vector<int> *timed = nullptr, size_t *ev = nullptr)
 {
     UpdateArgs a = update_args(L, b0, b1, nhit);
+    const bool fused = measure && fused_measure(L);
+    if (fused) a.meas = L->d_meas;
     const dim3 grid = update_grid(L), block(L->block);
     for (int p = 0; p < 2; ++p)
         for (int mu = 0; mu < L->nd; ++mu) {
             a.parity = p;
             a.mu = mu;
-            HIPCHK(launch_update(L->nd, L->prec, grid, block, st, a));
+            if (timed) HIPCHK(hipEventRecord(L->events[(*ev)++], st));
+            HIPCHK(launch_update(L->nd, L->prec, L->waves, grid, block, st, a));
+            if (timed) {
+                HIPCHK(hipEventRecord(L->events[(*ev)++], st));
+                timed->push_back(0);
+            }
         }
     HIPCHK(launch_counter_add(st, L->d_sweep, 1));
-    if (measure) return enqueue_plaquette(L, st, b0, b1, L->d_series);
+    if (!measure) return SU3HB_OK;
+    if (fused) {
+        if (timed) HIPCHK(hipEventRecord(L->events[(*ev)++], st));
+        HIPCHK(launch_measure_finalize(st, L->d_meas, L->nd, L->upd_blocks, double(L->reps[0].V), b0, L->d_plaq,
+                                       L->d_series, L->d_cursor));
+        if (timed) {
+            HIPCHK(hipEventRecord(L->events[(*ev)++], st));
+            timed->push_back(1);
+        }
+        return SU3HB_OK;
+    }
+    if (timed) HIPCHK(hipEventRecord(L->events[(*ev)++], st));
+    PlaqArgs pa;
+    std::memset(&pa, 0, sizeof pa);
+    pa.links = L->links;
+    pa.reps = L->d_reps;
+    pa.nrep = L->nrep;
+    pa.beta0 = b0;
+    pa.beta1 = b1;
+    pa.use_rep_beta = L->batch ? 1 : 0;
+    pa.partials = L->d_partials;
+    pa.total_blocks = L->plq_blocks;
+    HIPCHK(launch_plaquette(L->nd, L->prec, dim3(L->plq_blocks), dim3(kPlaqBlock), st, pa));
+    if (timed) {
+        HIPCHK(hipEventRecord(L->events[(*ev)++], st));
+        timed->push_back(1);
+    }
+    HIPCHK(launch_plaquette_finalize(st, L->d_reps, L->nrep, L->nd, L->d_partials, L->d_plaq, L->d_series,
+                                     L->d_cursor));
     return SU3HB_OK;
 }
 
@@ -340,6 +428,10 @@ int get_graph(su3hb_lattice *L, double b0, double b1, int nhit, int measure)
 int run_sweeps(su3hb_lattice *L, double b0, double b1, int nhit, int n, int measure)
 {
     if (n <= 0) return SU3HB_OK;
+    if (measure && fused_measure(L)) {
+        int rc = ensure_meas(L);
+        if (rc) return rc;
+    }
     if (L->use_graph) {
         int rc = get_graph(L, b0, b1, nhit, measure);
         if (rc) return rc;
@@ -459,14 +551,18 @@ std::string tune_key(const su3hb_lattice *L)
     return k;
 }
 
-int apply_launch(su3hb_lattice *L, int block, int xcd)
+int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
+    if (order < 0 || order > 2) return fail(SU3HB_EINVAL, "order = %d, expected 0, 1 or 2", order);
+    if (waves != 2 && !(waves == 3 && L->nd == 4))
+        return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
     drop_graph(L);
     L->block = block;
-    L->xcd = xcd ? 1 : 0;
+    L->order = order;
+    L->waves = waves;
     layout_reps(L);
     return upload_reps(L);
 }
@@ -531,8 +627,9 @@ int su3hb_init_lattice(su3hb_lattice **out, const su3hb_params *p)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(L));
         if (it != g_tune_cache.end()) {
-            L->block = it->second.first;
-            L->xcd = it->second.second;
+            L->block = it->second.block;
+            L->order = it->second.order;
+            L->waves = it->second.waves;
         }
     }
     rc = adopt_or_alloc_links(L, p->device_links, p->device_bytes);
@@ -642,18 +739,19 @@ int su3hb_set_state(su3hb_lattice *L, uint64_t seed, uint64_t sweep)
     return SU3HB_OK;
 }
 
-int su3hb_set_launch(su3hb_lattice *L, int block, int xcd_remap)
+int su3hb_set_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
     HIPCHK(hipSetDevice(L->device));
-    return apply_launch(L, block, xcd_remap);
+    return apply_launch(L, block, order, waves);
 }
 
-int su3hb_get_launch(const su3hb_lattice *L, int *block, int *xcd_remap)
+int su3hb_get_launch(const su3hb_lattice *L, int *block, int *order, int *waves)
 {
     if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
     if (block) *block = L->block;
-    if (xcd_remap) *xcd_remap = L->xcd;
+    if (order) *order = effective_order(L);
+    if (waves) *waves = L->waves;
     return SU3HB_OK;
 }
 
@@ -666,7 +764,8 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) return apply_launch(L, it->second.first, it->second.second);
+        if (it != g_tune_cache.end())
+            return apply_launch(L, it->second.block, it->second.order, it->second.waves);
     }
     // keep the state: links, sweep counter and statistics are restored below
     void *backup = nullptr;
@@ -678,18 +777,28 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     } guard{backup};
     HIPCHK(hipMemcpyAsync(backup, L->links, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
     const uint64_t sweep0 = L->sweep;
-    const int cands[6][2] = {{256, 1}, {128, 1}, {64, 1}, {256, 0}, {128, 0}, {64, 0}};
+    // candidate shapes: every block size and order, both occupancy targets for
+    // D = 4; order 2 only where it applies (otherwise it would repeat order 1)
+    std::vector<Shape> cands;
+    for (int waves : {2, 3}) {
+        if (waves == 3 && L->nd != 4) continue;
+        for (int block : {256, 128, 64})
+            for (int order : {0, 1, 2}) {
+                if (order == 2 && !slab_order_ok(L, block)) continue;
+                cands.push_back(Shape{block, order, waves});
+            }
+    }
     const double b = L->batch ? 0.0 : 6.0;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_i = 0;
+    size_t best_i = 0;
     const bool graph = L->use_graph;
     L->use_graph = false;
     int rc = SU3HB_OK;
-    for (int i = 0; i < 6 && !rc; ++i) {
-        rc = apply_launch(L, cands[i][0], cands[i][1]);
+    for (size_t i = 0; i < cands.size() && !rc; ++i) {
+        rc = apply_launch(L, cands[i].block, cands[i].order, cands[i].waves);
         if (rc) break;
         rc = enqueue_sweep(L, L->stream, b, b, 8, 0);  // warm-up
         if (rc) break;
@@ -704,7 +813,7 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
                 break;
             }
             hipEventElapsedTime(&ms, e0, e1);
-            if (ms * 6 * 2 >= budget_ms || reps >= 64) break;
+            if (ms * double(cands.size()) * 2 >= budget_ms || reps >= 64) break;
             reps *= 2;
         }
         if (rc) break;
@@ -725,9 +834,9 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = {cands[best_i][0], cands[best_i][1]};
+        g_tune_cache[key] = cands[best_i];
     }
-    return apply_launch(L, cands[best_i][0], cands[best_i][1]);
+    return apply_launch(L, cands[best_i].block, cands[best_i].order, cands[best_i].waves);
 }
 
 int su3hb_sweep_timed(su3hb_lattice *L, double beta0, double beta1, int n_hit, int n_sweeps, int measure,
@@ -741,53 +850,28 @@ int su3hb_sweep_timed(su3hb_lattice *L, double beta0, double beta1, int n_hit, i
     int rc = check_sweep_args(beta0, beta1, n_hit, n_sweeps);
     if (rc) return rc;
     HIPCHK(hipSetDevice(L->device));
-    const size_t upd_per = size_t(2 * L->nd), launches = size_t(n_sweeps) * (upd_per + (measure ? 1 : 0));
+    if (measure && fused_measure(L)) {
+        rc = ensure_meas(L);
+        if (rc) return rc;
+    }
+    const size_t launches = size_t(n_sweeps) * (size_t(2 * L->nd) + (measure ? 1 : 0));
     rc = ensure_events(L, 2 * launches);
     if (rc) return rc;
-    UpdateArgs a = update_args(L, beta0, beta1, n_hit);
-    const dim3 grid = update_grid(L), block(L->block);
     if (measure) HIPCHK(launch_counter_set(L->stream, L->d_cursor, 0));
     size_t ev = 0;
-    std::vector<int> is_plaq;
+    std::vector<int> kinds;
+    kinds.reserve(launches);
     for (int sw = 0; sw < n_sweeps; ++sw) {
-        for (int p = 0; p < 2; ++p)
-            for (int mu = 0; mu < L->nd; ++mu) {
-                a.parity = p;
-                a.mu = mu;
-                HIPCHK(hipEventRecord(L->events[ev], L->stream));
-                HIPCHK(launch_update(L->nd, L->prec, grid, block, L->stream, a));
-                HIPCHK(hipEventRecord(L->events[ev + 1], L->stream));
-                ev += 2;
-                is_plaq.push_back(0);
-            }
-        HIPCHK(launch_counter_add(L->stream, L->d_sweep, 1));
-        if (measure) {
-            PlaqArgs pa;
-            std::memset(&pa, 0, sizeof pa);
-            pa.links = L->links;
-            pa.reps = L->d_reps;
-            pa.nrep = L->nrep;
-            pa.beta0 = beta0;
-            pa.beta1 = beta1;
-            pa.use_rep_beta = L->batch ? 1 : 0;
-            pa.partials = L->d_partials;
-            pa.total_blocks = L->plq_blocks;
-            HIPCHK(hipEventRecord(L->events[ev], L->stream));
-            HIPCHK(launch_plaquette(L->nd, L->prec, dim3(L->plq_blocks), dim3(kPlaqBlock), L->stream, pa));
-            HIPCHK(hipEventRecord(L->events[ev + 1], L->stream));
-            ev += 2;
-            is_plaq.push_back(1);
-            HIPCHK(launch_plaquette_finalize(L->stream, L->d_reps, L->nrep, L->nd, L->d_partials, L->d_plaq,
-                                             L->d_series, L->d_cursor));
-        }
+        rc = enqueue_sweep(L, L->stream, beta0, beta1, n_hit, measure, &kinds, &ev);
+        if (rc) return rc;
     }
     L->sweep += uint64_t(n_sweeps);
     HIPCHK(hipStreamSynchronize(L->stream));
     double t_upd = 0, t_plq = 0, n_upd = 0, n_plq = 0;
-    for (size_t i = 0; i < is_plaq.size(); ++i) {
+    for (size_t i = 0; i < kinds.size(); ++i) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, L->events[2 * i], L->events[2 * i + 1]));
-        if (is_plaq[i]) {
+        if (kinds[i]) {
             t_plq += ms;
             n_plq += 1;
         } else {
@@ -839,8 +923,9 @@ int su3hb_batch_create(su3hb_batch **out, int nd, const su3hb_replica_desc *reps
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(L));
         if (it != g_tune_cache.end()) {
-            L->block = it->second.first;
-            L->xcd = it->second.second;
+            L->block = it->second.block;
+            L->order = it->second.order;
+            L->waves = it->second.waves;
         }
     }
     int rc = adopt_or_alloc_links(L, nullptr, 0);
@@ -875,7 +960,7 @@ int su3hb_batch_sweep(su3hb_batch *L, int n_hit, int n_sweeps, int mode, su3hb_s
         if (per_cu < 1) return fail(SU3HB_EUNSUPPORTED, "persistent kernel cannot be resident");
         const int blocks = int(std::min<uint64_t>(uint64_t(per_cu) * L->num_cus, L->upd_blocks));
         UpdateArgs a = update_args(L, 0.0, 0.0, n_hit);
-        a.xcd_remap = 0;
+        a.order = 0;
         HIPCHK(launch_update_persistent(L->nd, L->prec, blocks, L->block, L->stream, a, n_sweeps));
         HIPCHK(launch_counter_add(L->stream, L->d_sweep, uint32_t(n_sweeps)));
         L->sweep += uint64_t(n_sweeps);

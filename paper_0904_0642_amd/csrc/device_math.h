@@ -294,6 +294,25 @@ __device__ __forceinline__ void store_link(typename Store<PREC>::elem *__restric
 }
 
 
+// The FP64 matrix a link reads back as after store_link<PREC>(m): rounded to
+// the storage precision, with row 2 rebuilt for 12-real storage.
+template <int PREC>
+__device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
+{
+    using R = typename Store<PREC>::real;
+    if constexpr (Store<PREC>::NE == 9 && sizeof(R) == sizeof(double)) {
+        return m;
+    } else {
+        mat3<R> r;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) r.e[i][j] = cx<R>{R(m.e[i][j].re), R(m.e[i][j].im)};
+        if constexpr (Store<PREC>::NE == 6) third_row(r);
+        return widen<double>(r);
+    }
+}
+
 // Row i of a stored link (12-real storage: row 2 is rebuilt from rows 0, 1).
 template <int PREC>
 __device__ __forceinline__ void load_link_row(const typename Store<PREC>::elem *__restrict__ p, uint32_t Vh, int i,

@@ -7,8 +7,10 @@
 
 namespace su3hb {
 
-// checkerboard slice update (one colour, one direction, all replicas)
-hipError_t launch_update(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a);
+// checkerboard slice update (one colour, one direction, all replicas);
+// waves = minimum waves per SIMD the kernel was built for (2, or 3 for D = 4)
+hipError_t launch_update(int D, int prec, int waves, dim3 grid, dim3 block, hipStream_t st,
+                         const UpdateArgs &a);
 
 // persistent cooperative batch sweep: n_sweeps x 2D slices with a grid barrier
 hipError_t launch_update_persistent(int D, int prec, int blocks, int threads, hipStream_t st,
@@ -20,6 +22,11 @@ hipError_t launch_plaquette(int D, int prec, dim3 grid, dim3 block, hipStream_t 
 hipError_t launch_plaquette_finalize(hipStream_t st, const RepDesc *reps, int nrep, int D,
                                      const double *partials, double *out, double *series,
                                      uint32_t *series_cursor);
+
+// fused measurement of a single-layer lattice: sums the per-block plaquette
+// partials the parity-1 update slices wrote, normalises like the plaquette path
+hipError_t launch_measure_finalize(hipStream_t st, const double *meas, int D, uint32_t nblocks, double V,
+                                   double beta0, double *out, double *series, uint32_t *cursor);
 
 // start configuration of one replica: mode 1 ordered, 2 Haar
 hipError_t launch_start(int D, int prec, hipStream_t st, void *links, const RepDesc *reps, int r,

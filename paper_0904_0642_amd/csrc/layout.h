@@ -36,7 +36,7 @@ struct RepDesc {
     uint32_t upd_blocks;     // blocks of this replica in an update launch
     uint32_t plq_block0;     // first block in a plaquette launch
     uint32_t plq_blocks;
-    uint32_t plq_spt;        // sites per thread in the plaquette launch
+    uint32_t plq_spt;        // plaquettes per thread in the plaquette launch
 };
 
 // Statistics slot, padded to its own 128-byte line.
@@ -55,11 +55,15 @@ struct UpdateArgs {
     int mu;                      // direction being updated
     int nhit;                    // KP proposals per subgroup, at most
     int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
-    int xcd_remap;               // 1: renumber blocks XCD by XCD
+    int order;                   // block order: 0 hardware, 1 XCD-contiguous, 2 XCD slabs
+    uint32_t slab;               // order 2: extent of the last direction per XCD
+    uint32_t cp;                 // order 2: blocks per (x_{D-2}, x_{D-1}) plane
+    uint32_t n2;                 // order 2: extent of direction D-2
     double beta0, beta1;
     const uint32_t *sweep;       // device sweep counter
     StatSlot *stats;             // kStatSlots slots
     uint32_t total_blocks;       // real blocks (grid may be padded to 8)
+    double *meas;                // fused plaquettes: [mu][total_blocks] partial sums, or null
 };
 
 struct PlaqArgs {
@@ -71,5 +75,7 @@ struct PlaqArgs {
     double *partials;            // [block][5]
     uint32_t total_blocks;
 };
+
+constexpr int kDefaultWaves = 2;  // update kernels for D = 4 also exist for 3 waves/SIMD
 
 }  // namespace su3hb

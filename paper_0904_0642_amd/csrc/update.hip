@@ -92,9 +92,21 @@ __device__ __forceinline__ void su2_heatbath(mat3<double> &U, mat3<double> &W, u
     }
 }
 
+// Update one link.  On a single-layer lattice every plaquette carries beta0,
+// so the staple is summed unweighted and scaled once; on two layers each
+// staple gets the beta of its plaquette (tag rule).
+//
+// Fused measurement (single layer, parity 1, a.meas set): in slice (1, mu)
+// the staple terms of the planes (nu, mu) with nu < mu contain only links
+// that are final for this sweep once U_mu(x) is updated (directions below mu
+// finished their parity-1 slice, even-site U_mu finished in parity 0), and
+// every plaquette of such a plane holds exactly one odd-site U_mu link.  So
+// (1/3) Re Tr(U'_mu(x) A_{nu<mu}(x)) summed over the parity-1 slices counts
+// every plaquette of the end-of-sweep configuration exactly once.
 template <int D, int PREC>
 __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &rep, uint32_t lt,
-                                            uint32_t sweep, int att[3], int acc[3], double &dtrace)
+                                            uint32_t sweep, int att[3], int acc[3], double &dtrace,
+                                            double &plaq)
 {
     using R = typename Store<PREC>::real;
     const int p = a.parity, q = 1 - a.parity, mu = a.mu;
@@ -106,19 +118,25 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     }
     Site<D> x;
     x.from_half(rep, h, p, layer);
-    const uint32_t glued = rep.nlat == 2 ? rep.glued : 0u;
+    const bool single = rep.nlat == 1;
+    const uint32_t glued = single ? 0u : rep.glued;
     const double beta0 = a.use_rep_beta ? rep.beta0 : a.beta0;
     const double beta1 = a.use_rep_beta ? rep.beta1 : a.beta1;
+    const bool measure = a.meas != nullptr && p == 1 && single;
 
     // staple sum A = sum_{nu != mu} beta_f U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
     //                             + beta_b U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
     const Step fm = step_fwd<D>(rep, x, mu, glued);
     const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
-    mat3<R> A;
+    mat3<R> A, Alow;
     set_zero(A);
+    set_zero(Alow);
 #pragma unroll
     for (int nu = 0; nu < D; ++nu) {
-        if (nu == mu) continue;
+        if (nu == mu) {
+            if (measure) Alow = A;  // unweighted sum of the planes nu < mu
+            continue;
+        }
         const Step fn = step_fwd<D>(rep, x, nu, glued);
         const Step bn = step_bwd<D>(rep, x, nu, glued);
         const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
@@ -131,7 +149,7 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
             const mat3<R> u2 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, l_pn, mu, q, s_pn), Vh);
             const mat3<R> u3 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, layer, nu, p, x.s), Vh);
             acc_forward_staple<PREC>(A, link_ptr<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), u2, u3, Vh,
-                                     R(tags == 0 ? beta0 : beta1));
+                                     single ? R(1) : R(tags == 0 ? beta0 : beta1));
         }
         // backward staple: U_mu(x-nu) and U_nu(x-nu) streamed by rows
         {
@@ -139,9 +157,10 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
             const mat3<R> u2 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), Vh);
             acc_backward_staple<PREC>(A, link_ptr<D, PREC>(a.links, rep, l_mn, mu, q, s_mn), u2,
                                       link_ptr<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
-                                      R(tags == 0 ? beta0 : beta1));
+                                      single ? R(1) : R(tags == 0 ? beta0 : beta1));
         }
     }
+    if (single) scale(A, R(beta0));
 
     auto *uptr = link_ptr<D, PREC>(a.links, rep, layer, mu, p, x.s);
     mat3<double> U = widen<double>(load_link<PREC>(uptr, Vh));
@@ -155,12 +174,15 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     // W was rotated with U, so Re Tr W is now Re Tr(U' A)
     dtrace += (W.e[0][0].re + W.e[1][1].re + W.e[2][2].re - tr_old) * (1.0 / 3.0);
     reunitarize(U);
+    if (measure) plaq = re_tr_nn(stored_form<PREC>(U), widen<double>(Alow)) * (1.0 / 3.0);
     store_link<PREC>(uptr, Vh, U);
 }
 
-// Sum the per-thread counters over the block and add them to one slot.
-__device__ __forceinline__ void flush_stats(StatSlot *slots, uint32_t lb, int att[3], int acc[3], int upd,
-                                            double dtrace)
+// Sum the per-thread counters over the block and add them to one slot; with
+// a fused measurement also store the block's plaquette sum (plain store, one
+// slot per (direction, block), added up later in a fixed order).
+__device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, int att[3], int acc[3], int upd,
+                                            double dtrace, double plaq)
 {
     int v[7] = {att[0], att[1], att[2], acc[0], acc[1], acc[2], upd};
 #pragma unroll
@@ -168,14 +190,16 @@ __device__ __forceinline__ void flush_stats(StatSlot *slots, uint32_t lb, int at
 #pragma unroll
         for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], off);
         dtrace += __shfl_xor(dtrace, off);
+        plaq += __shfl_xor(plaq, off);
     }
     __shared__ int s_int[4][7];
-    __shared__ double s_dbl[4];
+    __shared__ double s_dbl[4][2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < 7; ++i) s_int[wave][i] = v[i];
-        s_dbl[wave] = dtrace;
+        s_dbl[wave][0] = dtrace;
+        s_dbl[wave][1] = plaq;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -183,9 +207,10 @@ __device__ __forceinline__ void flush_stats(StatSlot *slots, uint32_t lb, int at
         for (int w = 1; w < nw; ++w) {
 #pragma unroll
             for (int i = 0; i < 7; ++i) v[i] += s_int[w][i];
-            dtrace += s_dbl[w];
+            dtrace += s_dbl[w][0];
+            plaq += s_dbl[w][1];
         }
-        StatSlot *sl = &slots[lb % kStatSlots];
+        StatSlot *sl = &a.stats[lb % kStatSlots];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             atomicAdd(&sl->attempts[i], (unsigned long long)v[i]);
@@ -193,6 +218,8 @@ __device__ __forceinline__ void flush_stats(StatSlot *slots, uint32_t lb, int at
         }
         atomicAdd(&sl->updates, (unsigned long long)v[6]);
         unsafeAtomicAdd(&sl->dtrace, dtrace);
+        if (a.meas != nullptr && a.parity == 1 && lb < a.total_blocks)
+            a.meas[size_t(a.mu) * a.total_blocks + lb] = plaq;
     }
     __syncthreads();  // the shared arrays are reused by the next block in a persistent loop
 }
@@ -202,30 +229,44 @@ template <int D, int PREC>
 __device__ __forceinline__ void process_block(const UpdateArgs &a, uint32_t lb, uint32_t sweep)
 {
     int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
-    double dtrace = 0.0;
+    double dtrace = 0.0, plaq = 0.0;
     if (lb < a.total_blocks) {
         const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, false);
         const RepDesc &rep = a.reps[r];
         const uint32_t lt = (lb - rep.upd_block0) * blockDim.x + threadIdx.x;
         if (lt < rep.nlat * rep.Vh) {
-            update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace);
+            update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
             upd = 1;
         }
     }
-    flush_stats(a.stats, lb, att, acc, upd, dtrace);
+    flush_stats(a, lb, att, acc, upd, dtrace, plaq);
 }
 
-template <int D, int PREC>
-__global__ void __launch_bounds__(256) update_kernel(UpdateArgs a)
+// Logical block of hardware block b.  Hardware blocks are dealt round-robin
+// to the 8 XCDs.  Order 1 gives each XCD a contiguous run of logical blocks;
+// order 2 gives XCD k the slab k of the last direction and walks it with
+// that direction fastest, then the blocks of an (x_{D-2}, x_{D-1}) plane,
+// then x_{D-2}, so the neighbours of a block along the two slowest
+// directions are fetched by blocks that run next to it on the same L2.
+__device__ __forceinline__ uint32_t logical_block(const UpdateArgs &a, uint32_t b)
 {
-    uint32_t lb = blockIdx.x;
-    if (a.xcd_remap) {
-        // consecutive hardware blocks go round-robin over the 8 XCDs; give each
-        // XCD a contiguous run of logical blocks so neighbours share its L2
+    if (a.order == 1) {
         const uint32_t per = gridDim.x >> 3;
-        lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+        return (b & 7u) * per + (b >> 3);
     }
-    process_block<D, PREC>(a, lb, *a.sweep);
+    if (a.order == 2) {
+        const uint32_t k = b & 7u, e = b >> 3;
+        const uint32_t xl = e % a.slab, t = e / a.slab;
+        const uint32_t c = t % a.cp, x2 = t / a.cp;
+        return (x2 + a.n2 * (k * a.slab + xl)) * a.cp + c;
+    }
+    return b;
+}
+
+template <int D, int PREC, int WAVES>
+__global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
+{
+    process_block<D, PREC>(a, logical_block(a, blockIdx.x), *a.sweep);
 }
 
 // Persistent form for batches: the grid stays resident for n_sweeps sweeps,
@@ -253,19 +294,27 @@ __global__ void __launch_bounds__(256) update_persistent_kernel(UpdateArgs a, in
 }
 
 template <int D, int PREC>
-static hipError_t launch_update_t(dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
+static hipError_t launch_update_t(int waves, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
 {
-    hipLaunchKernelGGL((update_kernel<D, PREC>), grid, block, 0, st, a);
+    if (waves == 3) {
+        if constexpr (D == 4) {
+            hipLaunchKernelGGL((update_kernel<D, PREC, 3>), grid, block, 0, st, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
 template <int D>
-static hipError_t launch_update_d(int prec, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
+static hipError_t launch_update_d(int prec, int waves, dim3 grid, dim3 block, hipStream_t st,
+                                  const UpdateArgs &a)
 {
     switch (prec) {
-    case kFP64_18: return launch_update_t<D, kFP64_18>(grid, block, st, a);
-    case kFP32_18: return launch_update_t<D, kFP32_18>(grid, block, st, a);
-    case kFP32_12: return launch_update_t<D, kFP32_12>(grid, block, st, a);
+    case kFP64_18: return launch_update_t<D, kFP64_18>(waves, grid, block, st, a);
+    case kFP32_18: return launch_update_t<D, kFP32_18>(waves, grid, block, st, a);
+    case kFP32_12: return launch_update_t<D, kFP32_12>(waves, grid, block, st, a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -315,14 +364,15 @@ hipError_t launch_update_persistent(int D, int prec, int blocks, int threads, hi
     return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), params, 0, st);
 }
 
-hipError_t launch_update(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
+hipError_t launch_update(int D, int prec, int waves, dim3 grid, dim3 block, hipStream_t st,
+                         const UpdateArgs &a)
 {
     switch (D) {
-    case 2: return launch_update_d<2>(prec, grid, block, st, a);
-    case 3: return launch_update_d<3>(prec, grid, block, st, a);
-    case 4: return launch_update_d<4>(prec, grid, block, st, a);
-    case 5: return launch_update_d<5>(prec, grid, block, st, a);
-    case 6: return launch_update_d<6>(prec, grid, block, st, a);
+    case 2: return launch_update_d<2>(prec, waves, grid, block, st, a);
+    case 3: return launch_update_d<3>(prec, waves, grid, block, st, a);
+    case 4: return launch_update_d<4>(prec, waves, grid, block, st, a);
+    case 5: return launch_update_d<5>(prec, waves, grid, block, st, a);
+    case 6: return launch_update_d<6>(prec, waves, grid, block, st, a);
     default: return hipErrorInvalidValue;
     }
 }
