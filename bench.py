@@ -111,6 +111,113 @@ def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int):
     return out
 
 
+def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int = 128):
+    """Independent replicas of mixed sizes (8^4, 12^4, 16^3x4 round robin),
+    beta uniform in [5.5, 6.5], FP32 links, one launch per slice for all
+    replicas replayed from a HIP graph, and the same sweeps as one persistent
+    cooperative launch."""
+    import torch
+
+    import paper_0904_0642_amd as su3hb
+    from paper_0904_0642_amd import workloads
+
+    t = workloads.replica_table(nrep, seed=7)
+    reps = [(e, b, sd, st) for e, b, sd, st in zip(t.extents, t.betas, t.seeds, t.starts)]
+    prec = su3hb.FP32_18
+    b = su3hb.Batch(4, reps, precision=prec)
+    if autotune_ms > 0:
+        b.autotune(autotune_ms)
+    if warmup > 0:
+        b.sweep(n_hit=n_hit, n_sweeps=warmup, mode=0)
+    links = t.links_per_sweep
+    timing, _ = su3hb.su3hb_sweep_timed(b._h, 0.0, 0.0, n_hit, steps, measure=False)
+    upd_ms = timing[0] / max(timing[1], 1)
+    out = {}
+    for mode, label in ((0, "graph_per_slice"), (1, "persistent")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.sweep(n_hit=n_hit, n_sweeps=steps, mode=mode)
+        torch.cuda.synchronize()
+        out[label] = steps * links / (time.perf_counter() - t0)
+    plaq = b.plaquette()[:, 0]
+    S = BYTES_PER_LINK[prec]
+    bytes_per_launch = sum((2 * 4 + 1) * S * (int(np.prod(e)) // 2) for e in t.extents)
+    achieved = bytes_per_launch / (upd_ms * 1e-3) / 1e9
+    res = {"value": round(max(out.values()), 1), "unit": "link updates/s",
+           "by_mode": {k: round(v, 1) for k, v in out.items()},
+           "replicas": nrep, "links_per_sweep": links, "precision": PREC_NAME[prec],
+           "update_kernel_ms": round(upd_ms, 5),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": bytes_per_launch},
+           "plaquette_mean_over_replicas": float(np.mean(plaq)),
+           "launch": dict(zip(("block", "order", "waves"), su3hb.su3hb_get_launch(b._h)))}
+    b.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def dlt_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int):
+    """Double-layered torus: two 24^3 x 8 layers glued in all directions,
+    beta0 = beta1 = 5.69, FP32 links, plaquettes every sweep."""
+    import torch
+
+    import paper_0904_0642_amd as su3hb
+
+    ext, beta = (24, 24, 24, 8), 5.69
+    lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0xF, precision=su3hb.FP32_18, seed=1)
+    if autotune_ms > 0:
+        lat.autotune(autotune_ms)
+    if warmup > 0:
+        lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timing, series = lat.sweep_timed(beta, n_hit=n_hit, n_sweeps=steps, measure=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    links = 2 * int(np.prod(ext)) * 4
+    res = {"value": round(steps * links / secs, 1), "unit": "link updates/s", "links_per_sweep": links,
+           "update_kernel_ms": round(timing[0] / max(timing[1], 1), 5),
+           "plaquette_kernel_ms": round(timing[2] / max(timing[3], 1), 5),
+           "plaquette_first_last": [float(series[0, 0]), float(series[-1, 0])],
+           "layers_last": [float(series[-1, 3]), float(series[-1, 4])]}
+    lat.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
+    """Equal-volume comparison at equal sweep count (hence equal statistical
+    error of <P>): 32^4 at beta = 6.0, same seed, FP64-18 / FP32-18 / FP32-12."""
+    import torch
+
+    import paper_0904_0642_amd as su3hb
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from stats import jackknife_mean
+
+    ext, beta = (32, 32, 32, 32), 6.0
+    links = int(np.prod(ext)) * 4
+    res = {"lattice": list(ext), "beta": beta, "thermalisation_sweeps": ntherm, "measured_sweeps": nmeas}
+    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
+        lat = su3hb.Lattice(ext, precision=prec, seed=11)
+        lat.autotune(200)
+        lat.sweep(beta, n_hit=n_hit, n_sweeps=ntherm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=nmeas)
+        secs = time.perf_counter() - t0
+        m, e = jackknife_mean(ser[:, 0], 20)
+        res[PREC_NAME[prec]] = {"rate": round(nmeas * links / secs, 1), "plaquette": m, "error": e}
+        lat.close()
+        torch.cuda.empty_cache()
+    ref = res["fp64-18"]
+    for k in ("fp32-18", "fp32-12"):
+        r = res[k]
+        r["speedup_vs_fp64_at_equal_error"] = round(r["rate"] / ref["rate"], 3)
+        r["delta_vs_fp64_in_sigma"] = round((r["plaquette"] - ref["plaquette"]) / np.hypot(r["error"], ref["error"]), 2)
+    return res
+
+
 def cpu_baseline(name: str, n_hit: int):
     """The FP64 oracle on a bounded sample of the same workload: the first two
     checkerboard slices (parity 0, directions 0 and 1) of the hot-started
@@ -143,6 +250,7 @@ def main():
     ap.add_argument("--n-hit", type=int, default=8)
     ap.add_argument("--autotune-ms", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true", help="skip the batch, DLT and precision legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()
@@ -207,6 +315,10 @@ def main():
             "plaquette_first_last": leg["plaquette_first_last"],
             "rate_ratio_vs_main": round(leg["rate"] / main_leg["rate"], 3),
         }
+    if not args.no_extra_legs:
+        line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
+        line["dlt_2x24^3x8_fp32"] = dlt_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
+        line["precision_study"] = precision_study(args.n_hit)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.n_hit)
     print(json.dumps(line), flush=True)

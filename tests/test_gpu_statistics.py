@@ -1,0 +1,158 @@
+"""Long GPU runs against exact results and the paper's statistics.
+
+Error bars are 32-bin jackknife errors of the per-sweep plaquette series;
+comparisons use the Gaussian difference test of the paper (Sec. 3.2): two
+estimates agree when Q = erfc(|m1-m2| / sqrt(2 (e1^2 + e2^2))) is not tiny.
+Every run is seeded, so each test is deterministic.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_0904_0642_amd as su3hb
+from exact_su3 import u_exact
+from stats import gaussian_difference_q, jackknife_mean
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+QMIN = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    su3hb.lib()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_series(lat, beta0, beta1=None, n_hit=8, ntherm=200, nmeas=4000, col=0):
+    lat.sweep(beta0, beta1, n_hit=n_hit, n_sweeps=ntherm)
+    s = lat.sweep_measure(beta0, beta1, n_hit=n_hit, n_sweeps=nmeas)
+    return s[:, col] if isinstance(col, int) else s[:, col]
+
+
+def test_2d_32x32_exact():
+    # D = 2 torus 32^2 at beta = 4: <P> = u(4) = 0.27961914940930...
+    lat = su3hb.Lattice([32, 32], seed=1)
+    s = run_series(lat, 4.0, ntherm=200, nmeas=20000)
+    m, e = jackknife_mean(s, 32)
+    say(f"  2D 32^2 beta=4: <P> = {m:.6f} +- {e:.6f}, exact {u_exact(4.0):.6f}")
+    assert gaussian_difference_q(m, e, u_exact(4.0), 0.0) > QMIN
+
+
+@pytest.mark.parametrize("mask", [0b11, 0b01])
+def test_2d_double_layered_exact(mask):
+    lat = su3hb.Lattice([16, 16], nlat=2, dlt_mask=mask, seed=2)
+    s = run_series(lat, 4.0, ntherm=200, nmeas=10000)
+    m, e = jackknife_mean(s, 32)
+    say(f"  2D DLT mask={mask:02b} beta=4: <P> = {m:.6f} +- {e:.6f}")
+    assert gaussian_difference_q(m, e, u_exact(4.0), 0.0) > QMIN
+
+
+def test_4d_strong_coupling():
+    lat = su3hb.Lattice([8, 8, 8, 8], seed=3)
+    s = run_series(lat, 1.0, ntherm=100, nmeas=3000)
+    m, e = jackknife_mean(s, 32)
+    say(f"  4D beta=1: <P> = {m:.6f} +- {e:.6f}, u(1) = {u_exact(1.0):.6f}")
+    assert gaussian_difference_q(m, e, u_exact(1.0), 2e-6) > QMIN
+
+
+def test_paper_4x4x4x4_beta5p6_ordered():
+    # Sec. 3.2: 4^4, beta = 5.6, ordered start, (1STAT) statistics:
+    # act = 0.53770(18) single-processor, 0.53811(19) MPI
+    ref = GOLDEN["pbc_4x4x4x4_b5.6_ordered"]
+    st = GOLDEN["statistics_1STAT"]
+    lat = su3hb.Lattice(ref["extents"], start=su3hb.COLD, seed=5)
+    lat.sweep(ref["beta"], n_hit=1, n_sweeps=st["nequi"])
+    s = lat.sweep_measure(ref["beta"], n_hit=1, n_sweeps=st["nrpt"] * st["nmeas"] * st["nsw"])[:, 0]
+    m, e = jackknife_mean(s, 32)
+    q1 = gaussian_difference_q(m, e, *ref["act_single"])
+    q2 = gaussian_difference_q(m, e, *ref["act_mpi"])
+    say(f"  4^4 beta=5.6: act = {m:.5f}({e*1e5:.0f}); paper {ref['act_single']} Q={q1:.2f}, {ref['act_mpi']} Q={q2:.2f}")
+    assert max(q1, q2) > QMIN
+
+
+def test_paper_table1_8x8x8x4():
+    ref = GOLDEN["pbc_8x8x8x4_b5.65"]
+    lat = su3hb.Lattice(ref["extents"], start=su3hb.COLD, seed=6)
+    s = run_series(lat, ref["beta"], n_hit=1, ntherm=4096, nmeas=32 * 1024 * 2)
+    m, e = jackknife_mean(s, 32)
+    qs = [gaussian_difference_q(m, e, *v) for v in ref["actm"]]
+    say(f"  8^3 4 beta=5.65: act = {m:.6f}({e*1e6:.0f}); Q vs Table 1 rows = {[round(q, 2) for q in qs]}")
+    assert qs[0] > QMIN
+
+
+def test_paper_table2_16x16x16x4():
+    ref = GOLDEN["pbc_16x16x16x4_b5.65"]
+    lat = su3hb.Lattice(ref["extents"], start=su3hb.COLD, seed=7)
+    lat.sweep(ref["beta"], n_hit=1, n_sweeps=4096)
+    ser = lat.sweep_measure(ref["beta"], n_hit=1, n_sweeps=32 * 1024 * 2)
+    ms, es = jackknife_mean(ser[:, 1], 32)
+    mt, et = jackknife_mean(ser[:, 2], 32)
+    qs = gaussian_difference_q(ms, es, *ref["spacelike_single"])
+    qt = gaussian_difference_q(mt, et, *ref["timelike_single"])
+    say(f"  16^3 4 beta=5.65: spacelike {ms:.6f}({es*1e6:.0f}) Q={qs:.2f}; timelike {mt:.6f}({et*1e6:.0f}) Q={qt:.2f}")
+    assert qs > QMIN and qt > QMIN
+
+
+def test_paper_table3_dlt_8x8x8x4():
+    ref = GOLDEN["dlt_8x8x8x4_b5.55_disordered"]
+    lat = su3hb.Lattice(ref["extents"], nlat=2, dlt_mask=0b1111, start=su3hb.HOT, seed=8)
+    s = run_series(lat, ref["beta"], n_hit=1, ntherm=4096, nmeas=32 * 512 * 2)
+    m, e = jackknife_mean(s, 32)
+    qs = [gaussian_difference_q(m, e, *v) for v in ref["actm"]]
+    say(f"  DLT 8^3 4 beta=5.55: act = {m:.6f}({e*1e6:.0f}); Q vs Table 3 rows = {[round(q, 2) for q in qs]}")
+    assert max(qs) > QMIN
+
+
+def test_long_run_gpu_vs_oracle(oracle_mod):
+    # 4^4, beta = 6.0, ordered start, n_hit = 8 (the small workload): the GPU
+    # chain and an independent oracle chain (other seed) agree statistically
+    lat = su3hb.Lattice([4, 4, 4, 4], start=su3hb.COLD, seed=1)
+    sg = run_series(lat, 6.0, ntherm=500, nmeas=32000)
+    mg, eg = jackknife_mean(sg, 32)
+    o = oracle_mod.Lattice([4, 4, 4, 4], seed=2)
+    o.cold_start()
+    o.sweep(6.0, nhit=8, nsweeps=500)
+    so = []
+    for _ in range(4000):
+        o.sweep(6.0, nhit=8, nsweeps=1)
+        so.append(o.plaquette(6.0)[0])
+    mo, eo = jackknife_mean(np.array(so), 32)
+    q = gaussian_difference_q(mg, eg, mo, eo)
+    say(f"  4^4 beta=6: GPU {mg:.5f}({eg*1e5:.0f}) oracle {mo:.5f}({eo*1e5:.0f}) Q={q:.2f}")
+    assert abs(mg - mo) < 3 * np.hypot(eg, eo)
+
+
+def test_acceptance_near_97_percent():
+    # Sec. 2.1: the 1-hit acceptance is around 97% in the scaling region
+    lat = su3hb.Lattice([16, 16, 16, 16], seed=9)
+    lat.sweep(6.0, n_hit=1, n_sweeps=100)
+    st = lat.sweep(6.0, n_hit=1, n_sweeps=20, stats=True)
+    acc = np.array(st["accepts"]) / np.array(st["attempts"])
+    say(f"  16^4 beta=6.0 1-hit acceptance per subgroup: {acc}")
+    assert np.all(acc > 0.95) and np.all(acc < 0.995)
+
+
+def test_fp32_vs_fp64_same_plaquette():
+    # FP32 link storage (FP64 heatbath, reunitarisation, accumulation) gives
+    # the same <P> as FP64 within the statistical error of equal-length runs
+    res = {}
+    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
+        lat = su3hb.Lattice([16, 16, 16, 16], seed=10, precision=prec)
+        s = run_series(lat, 6.0, ntherm=300, nmeas=3000)
+        res[prec] = jackknife_mean(s, 32)
+    (m64, e64) = res[su3hb.FP64_18]
+    for prec in (su3hb.FP32_18, su3hb.FP32_12):
+        m, e = res[prec]
+        say(f"  16^4 beta=6.0 prec={prec}: {m:.6f}({e*1e6:.0f}) vs FP64 {m64:.6f}({e64*1e6:.0f})")
+        assert abs(m - m64) < 3 * np.hypot(e, e64)
