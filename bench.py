@@ -39,11 +39,13 @@ WORKLOADS = {
     "48^4-fp64": ((48, 48, 48, 48), 0, 6.2),
     "64^4-fp32-12": ((64, 64, 64, 64), 2, 6.2),
     "64^4-fp32-18": ((64, 64, 64, 64), 1, 6.2),
+    "48^4-fp64-12": ((48, 48, 48, 48), 3, 6.2),
     "16^4-fp64": ((16, 16, 16, 16), 0, 6.0),
 }
-PREC_NAME = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12"}
-PREC_DTYPE = {0: "f64", 1: "f32 links + f64 heatbath", 2: "f32 (12-real) links + f64 heatbath"}
-BYTES_PER_LINK = {0: 144, 1: 72, 2: 48}
+PREC_NAME = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12", 3: "fp64-12"}
+PREC_DTYPE = {0: "f64", 1: "f32 links + f64 heatbath", 2: "f32 (12-real) links + f64 heatbath",
+              3: "f64 (12-real links)"}
+BYTES_PER_LINK = {0: 144, 1: 72, 2: 48, 3: 96}
 
 
 def kernel_source_hash() -> str:
@@ -65,7 +67,14 @@ def measured_traffic(workload: str, algorithmic_bytes: float):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int):
+def parse_launch(text: str):
+    if not text:
+        return None
+    b, o, w = (int(v) for v in text.split(","))
+    return b, o, w
+
+
+def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int, launch=None):
     import torch
 
     import paper_0904_0642_amd as su3hb
@@ -74,7 +83,9 @@ def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int):
     D = len(ext)
     V = int(np.prod(ext))
     lat = su3hb.Lattice(ext, precision=prec, start=su3hb.HOT, seed=1)
-    if autotune_ms > 0:
+    if launch is not None:
+        lat.set_launch(*launch)
+    elif autotune_ms > 0:
         lat.autotune(autotune_ms)
     block, order, waves = lat.get_launch()
     if warmup > 0:
@@ -187,7 +198,7 @@ def dlt_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int):
 
 def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
     """Equal-volume comparison at equal sweep count (hence equal statistical
-    error of <P>): 32^4 at beta = 6.0, same seed, FP64-18 / FP32-18 / FP32-12."""
+    error of <P>): 32^4 at beta = 6.0, same seed, FP64-18 / FP64-12 / FP32-18 / FP32-12."""
     import torch
 
     import paper_0904_0642_amd as su3hb
@@ -198,7 +209,7 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
     ext, beta = (32, 32, 32, 32), 6.0
     links = int(np.prod(ext)) * 4
     res = {"lattice": list(ext), "beta": beta, "thermalisation_sweeps": ntherm, "measured_sweeps": nmeas}
-    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
+    for prec in (su3hb.FP64_18, su3hb.FP64_12, su3hb.FP32_18, su3hb.FP32_12):
         lat = su3hb.Lattice(ext, precision=prec, seed=11)
         lat.autotune(200)
         lat.sweep(beta, n_hit=n_hit, n_sweeps=ntherm)
@@ -211,7 +222,7 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
         lat.close()
         torch.cuda.empty_cache()
     ref = res["fp64-18"]
-    for k in ("fp32-18", "fp32-12"):
+    for k in ("fp64-12", "fp32-18", "fp32-12"):
         r = res[k]
         r["speedup_vs_fp64_at_equal_error"] = round(r["rate"] / ref["rate"], 3)
         r["delta_vs_fp64_in_sigma"] = round((r["plaquette"] - ref["plaquette"]) / np.hypot(r["error"], ref["error"]), 2)
@@ -249,6 +260,8 @@ def main():
     ap.add_argument("--compare", default="64^4-fp32-12", help="second leg ('' to skip)")
     ap.add_argument("--n-hit", type=int, default=8)
     ap.add_argument("--autotune-ms", type=int, default=400)
+    ap.add_argument("--launch", default="", help="block,order,waves for the main leg instead of autotuning")
+    ap.add_argument("--compare-launch", default="", help="block,order,waves for the comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true", help="skip the batch, DLT and precision legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -278,10 +291,12 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
-    main_leg = run_leg(args.workload, args.steps, args.warmup, args.n_hit, args.autotune_ms)
+    main_leg = run_leg(args.workload, args.steps, args.warmup, args.n_hit, args.autotune_ms,
+                       parse_launch(args.launch))
     legs = {}
     if args.compare and args.compare != args.workload:
-        legs[args.compare] = run_leg(args.compare, args.steps, args.warmup, args.n_hit, args.autotune_ms)
+        legs[args.compare] = run_leg(args.compare, args.steps, args.warmup, args.n_hit, args.autotune_ms,
+                                     parse_launch(args.compare_launch))
 
     ext, prec, beta = WORKLOADS[args.workload]
     line = {

@@ -44,14 +44,16 @@ typedef enum su3hb_status {
     SU3HB_EUNSUPPORTED = -5 /* valid request the GPU build does not cover     */
 } su3hb_status;
 
-/* Link storage.  Heatbath draws, reunitarisation and every accumulation run
- * in FP64 in all three modes; FP32 modes store the links and form the staple
- * products in FP32.  12-real storage keeps rows 0 and 1 and rebuilds
- * row 2 = conj(row0 x row1) on load. */
+/* Link storage.  The Kennedy-Pendleton draw and acceptance test,
+ * reunitarisation and every accumulation run in FP64 in all modes; FP32
+ * modes store the links and form the staple products, W = U A, the random
+ * direction and the SU(2) rotations in FP32.  12-real storage keeps rows 0
+ * and 1 and rebuilds row 2 = conj(row0 x row1) on load. */
 typedef enum su3hb_precision {
     SU3HB_FP64_18 = 0,  /* 144 bytes per link */
     SU3HB_FP32_18 = 1,  /*  72 bytes per link */
-    SU3HB_FP32_12 = 2   /*  48 bytes per link */
+    SU3HB_FP32_12 = 2,  /*  48 bytes per link */
+    SU3HB_FP64_12 = 3   /*  96 bytes per link, FP64 arithmetic throughout */
 } su3hb_precision;
 
 /* Start configuration (istart of mc.par, Sec. 2.3). */
@@ -143,7 +145,7 @@ int su3hb_get_links(const su3hb_lattice *lat, double *host, size_t n);
 
 /* Replace the links from host memory in the canonical layout.  Every matrix
  * is checked on the GPU first: a NaN/Inf entry, or max|U U^dag - 1| or
- * |det U - 1| above 1e-10 (FP64) / 1e-6 (FP32 modes) returns SU3HB_ENOTSU3
+ * |det U - 1| above 1e-10 (FP64 modes) / 1e-6 (FP32 modes) returns SU3HB_ENOTSU3
  * and leaves the lattice unchanged.  Synchronises. */
 int su3hb_set_links(su3hb_lattice *lat, const double *host, size_t n);
 
@@ -156,10 +158,14 @@ int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
 /* Launch shape of the update kernel.  block: threads per block (64, 128 or
  * 256).  order: 0 = hardware block order; 1 = each XCD gets a contiguous run
  * of blocks; 2 = each of the 8 XCDs gets a slab of the last direction and
- * walks it with that direction fastest (applies to one single-layer lattice
- * whose last extent is a multiple of 8 and whose blocks tile an
- * (x_{D-2}, x_{D-1}) plane; elsewhere it acts as 1).  waves: minimum waves
- * per SIMD the kernel is compiled for, 2, or 3 (D = 4 only).  Results are
+ * walks it with that direction fastest (one single-layer lattice whose last
+ * extent is a multiple of 8 and whose blocks tile an (x_{D-2}, x_{D-1})
+ * plane); 3 = as 2, with the waves of a block stacked along the two slowest
+ * directions (2 x 2 waves for 256 threads, 1 x 2 for 128; needs planes of a
+ * multiple of 64 half-sites); 4 = as 2, walking the block's chunk of the
+ * plane slowest and x_{D-2} in the middle.  Where an order does not apply
+ * a lower one that does is used (4 and 2 fall back to 1, 3 to 2 or 1).  waves: minimum waves per SIMD the kernel is
+ * compiled for: 2; 3 for D = 4; 4 for D = 4 with FP32 links.  Results are
  * bit-identical for every shape.  get_launch reports the order in effect. */
 int su3hb_set_launch(su3hb_lattice *lat, int block, int order, int waves);
 int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *order, int *waves);

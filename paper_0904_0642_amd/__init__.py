@@ -14,14 +14,14 @@ import os
 import numpy as np
 
 from . import workloads  # noqa: F401  (seeded inputs, presets)
-from .workloads import COLD, FP32_12, FP32_18, FP64_18, HOT  # noqa: F401
+from .workloads import COLD, FP32_12, FP32_18, FP64_12, FP64_18, HOT  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsu3hb.so")
 MAX_D = 8
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSU3, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-BYTES_PER_LINK = {FP64_18: 144, FP32_18: 72, FP32_12: 48}
+BYTES_PER_LINK = {FP64_18: 144, FP32_18: 72, FP32_12: 48, FP64_12: 96}
 
 
 class su3hb_params(C.Structure):

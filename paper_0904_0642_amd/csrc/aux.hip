@@ -33,24 +33,6 @@ __device__ __forceinline__ void block_sum(double v[NV])
     }
 }
 
-// Row i of a link, widened to FP64 (12-real storage rebuilds row 2).
-template <int PREC>
-__device__ __forceinline__ void load_row(const typename Store<PREC>::elem *__restrict__ p, uint32_t Vh, int i,
-                                         cx<double> r[3])
-{
-    if (Store<PREC>::NE == 6 && i == 2) {
-        const mat3<double> m = widen<double>(load_link<PREC>(p, Vh));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] = m.e[2][c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const auto v = p[size_t(3 * i + c) * Vh];
-            r[c] = cx<double>{double(v.x), double(v.y)};
-        }
-    }
-}
-
 // One thread per site (`spt` sites per thread, strided by the block size):
 // the D(D-1)/2 plaquettes based at x,
 // (1/3) Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = (1/3) Re Tr(T1 T2^dag)
@@ -87,16 +69,16 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
                 const Step fm = step_fwd<D>(rep, x, mu, glued);
                 const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
                 const mat3<double> umx = widen<double>(
-                    load_link<PREC>(link_ptr<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh));
+                    load_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh));
 #pragma unroll
                 for (int nu = mu + 1; nu < D; ++nu) {
                     const Step fn = step_fwd<D>(rep, x, nu, glued);
                     const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
                     const mat3<double> t1 = mul_nn(
-                        umx, widen<double>(load_link<PREC>(link_ptr<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh)));
+                        umx, widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh)));
                     const mat3<double> t2 = mul_nn(
-                        widen<double>(load_link<PREC>(link_ptr<D, PREC>(links, rep, layer, nu, p, x.s), rep.Vh)),
-                        widen<double>(load_link<PREC>(link_ptr<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh)));
+                        widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, nu, p, x.s), rep.Vh)),
+                        widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh)));
                     const double P = re_tr_na(t1, t2) * (1.0 / 3.0);
                     if (nu == D - 1) v[1] += P; else v[0] += P;
                     site_sum += P;
@@ -215,6 +197,7 @@ hipError_t launch_plaquette(int D, int prec, dim3 g, dim3 b, hipStream_t st, con
         case kFP64_18: return launch_plaquette_t<DD, kFP64_18>(g, b, st, a);      \
         case kFP32_18: return launch_plaquette_t<DD, kFP32_18>(g, b, st, a);      \
         case kFP32_12: return launch_plaquette_t<DD, kFP32_12>(g, b, st, a);      \
+        case kFP64_12: return launch_plaquette_t<DD, kFP64_12>(g, b, st, a);      \
         default: return hipErrorInvalidValue;                                     \
         }
     switch (D) {
@@ -288,7 +271,7 @@ __global__ void __launch_bounds__(256) start_kernel(void *links, const RepDesc *
         }
         reunitarize(u);
     }
-    store_link<PREC>(link_ptr<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh, u);
+    store_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh, u);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,7 +306,7 @@ __global__ void __launch_bounds__(256) pack_kernel(const void *links, const RepD
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         const mat3<double> u = widen<double>(
-            load_link<PREC>(link_ptr<D, PREC>(const_cast<void *>(links), rep, layer, mu, p, s), rep.Vh));
+            load_link<PREC>(link_ref<D, PREC>(const_cast<void *>(links), rep, layer, mu, p, s), rep.Vh));
         double *o = dst + (size_t(t) * D + mu) * 18;
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
@@ -352,7 +335,7 @@ __global__ void __launch_bounds__(256) unpack_kernel(void *links, const RepDesc 
         mat3<double> u;
 #pragma unroll
         for (int e = 0; e < 9; ++e) u.e[e / 3][e % 3] = cx<double>{in[2 * e], in[2 * e + 1]};
-        store_link<PREC>(link_ptr<D, PREC>(links, rep, layer, mu, p, s), rep.Vh, u);
+        store_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, s), rep.Vh, u);
     }
 }
 
@@ -370,6 +353,7 @@ __global__ void __launch_bounds__(256) unpack_kernel(void *links, const RepDesc 
     case kFP64_18: hipLaunchKernelGGL((KERNEL<DD, kFP64_18>), __VA_ARGS__); break;         \
     case kFP32_18: hipLaunchKernelGGL((KERNEL<DD, kFP32_18>), __VA_ARGS__); break;         \
     case kFP32_12: hipLaunchKernelGGL((KERNEL<DD, kFP32_12>), __VA_ARGS__); break;         \
+    case kFP64_12: hipLaunchKernelGGL((KERNEL<DD, kFP64_12>), __VA_ARGS__); break;         \
     default: return hipErrorInvalidValue;                                                  \
     }                                                                                      \
     break;

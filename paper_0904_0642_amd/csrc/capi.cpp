@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/su3hb.h"
+#include "su3hb.h"
 #include "kernels.h"
 #include "layout.h"
 
@@ -267,9 +267,31 @@ bool slab_order_ok(const su3hb_lattice *L, int block)
     return plane % uint32_t(block) == 0;
 }
 
+// Order 3 (3D blocks: tile2 x tile3 waves along x_{D-2}, x_{D-1}) needs one
+// single-layer lattice whose (x_{D-2}, x_{D-1}) planes hold a multiple of 64
+// half-sites, n_{D-2} divisible by tile2 and n_{D-1} by 8 tile3.
+void cube_tiles(int block, uint32_t *t2, uint32_t *t3)
+{
+    *t2 = block == 256 ? 2u : 1u;
+    *t3 = uint32_t(block) / 64u / *t2;
+}
+
+bool cube_order_ok(const su3hb_lattice *L, int block)
+{
+    if (L->batch || L->nrep != 1 || L->nd < 3) return false;
+    const RepDesc &r = L->reps[0];
+    if (r.nlat != 1) return false;
+    const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
+    const uint32_t plane = r.Vh / (nl * n2);
+    uint32_t t2, t3;
+    cube_tiles(block, &t2, &t3);
+    return plane % 64u == 0 && n2 % t2 == 0 && nl % (8u * t3) == 0;
+}
+
 int effective_order(const su3hb_lattice *L)
 {
-    if (L->order == 2 && !slab_order_ok(L, L->block)) return 1;
+    if (L->order == 3 && !cube_order_ok(L, L->block)) return slab_order_ok(L, L->block) ? 2 : 1;
+    if ((L->order == 2 || L->order == 4) && !slab_order_ok(L, L->block)) return 1;
     return L->order;
 }
 
@@ -283,12 +305,19 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
     a.nhit = nhit;
     a.use_rep_beta = L->batch ? 1 : 0;
     a.order = effective_order(L);
-    if (a.order == 2) {
+    if (a.order >= 2) {
         const RepDesc &r = L->reps[0];
         const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
-        a.slab = nl / 8;
-        a.cp = r.Vh / (nl * n2) / uint32_t(L->block);
         a.n2 = n2;
+        a.plane = r.Vh / (nl * n2);
+        if (a.order == 2 || a.order == 4) {
+            a.slab = nl / 8;
+            a.cp = a.plane / uint32_t(L->block);
+        } else {
+            cube_tiles(L->block, &a.tile2, &a.tile3);
+            a.slab = nl / (8u * a.tile3);
+            a.cp = a.plane / 64u;
+        }
     }
     a.beta0 = b0;
     a.beta1 = b1;
@@ -509,7 +538,7 @@ int set_replica_links(su3hb_lattice *L, int r, const double *host, size_t n)
         return fail(SU3HB_EINVAL, "n = %zu, expected nlat*V*D*18 = %zu", n, size_t(nsites * per_site));
     int rc = ensure_stage(L);
     if (rc) return rc;
-    const double tol = L->prec == kFP64_18 ? 1e-10 : 1e-6;
+    const double tol = is_fp32(L->prec) ? 1e-6 : 1e-10;
     const uint64_t chunk = kStageBytes / (per_site * sizeof(double));
     const bool single = nsites <= chunk;
     // pass 1: validate every matrix on the GPU before anything is written
@@ -555,9 +584,9 @@ int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
-    if (order < 0 || order > 2) return fail(SU3HB_EINVAL, "order = %d, expected 0, 1 or 2", order);
-    if (waves != 2 && !(waves == 3 && L->nd == 4))
-        return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4", waves);
+    if (order < 0 || order > 4) return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 4", order);
+    if (waves != 2 && !(waves == 3 && L->nd == 4) && !(waves == 4 && L->nd == 4 && is_fp32(L->prec)))
+        return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4, or 4 for D = 4 with FP32 links", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
     drop_graph(L);
     L->block = block;
@@ -592,7 +621,7 @@ int su3hb_links_bytes(const su3hb_params *p, size_t *bytes)
     int rc = check_extents(p->nd, p->extents, &V);
     if (rc) return rc;
     if (p->nlat != 1 && p->nlat != 2) return fail(SU3HB_EINVAL, "nlat = %d, expected 1 or 2", p->nlat);
-    if (p->precision < 0 || p->precision > 2) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
+    if (p->precision < 0 || p->precision > 3) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
     *bytes = size_t(p->nlat) * p->nd * V * size_t(bytes_per_link(p->precision));
     return SU3HB_OK;
 }
@@ -609,7 +638,7 @@ int su3hb_init_lattice(su3hb_lattice **out, const su3hb_params *p)
     if (p->nlat == 1 && (p->dlt_mask != 0 || p->lat2test))
         return fail(SU3HB_EINVAL, "dlt_mask and lat2test need nlat = 2");
     if (p->dlt_mask >> p->nd) return fail(SU3HB_EINVAL, "dlt_mask has bits beyond direction %d", p->nd - 1);
-    if (p->precision < 0 || p->precision > 2) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
+    if (p->precision < 0 || p->precision > 3) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
     if (p->start < 0 || p->start > 2) return fail(SU3HB_EINVAL, "unknown start %d", p->start);
     if (double(p->nlat) * double(V) * p->nd > 4294967295.0)
         return fail(SU3HB_EINVAL, "more than 2^32 links: the Philox counter holds a 32-bit link id");
@@ -778,13 +807,16 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     HIPCHK(hipMemcpyAsync(backup, L->links, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
     const uint64_t sweep0 = L->sweep;
     // candidate shapes: every block size and order, both occupancy targets for
-    // D = 4; order 2 only where it applies (otherwise it would repeat order 1)
+    // D = 4; orders 2 and 3 only where they apply (otherwise they would repeat
+    // another order), order 3 only with more than one wave per block
     std::vector<Shape> cands;
-    for (int waves : {2, 3}) {
-        if (waves == 3 && L->nd != 4) continue;
+    for (int waves : {2, 3, 4}) {
+        if (waves >= 3 && L->nd != 4) continue;
+        if (waves == 4 && !is_fp32(L->prec)) continue;
         for (int block : {256, 128, 64})
-            for (int order : {0, 1, 2}) {
-                if (order == 2 && !slab_order_ok(L, block)) continue;
+            for (int order : {0, 1, 2, 3, 4}) {
+                if ((order == 2 || order == 4) && !slab_order_ok(L, block)) continue;
+                if (order == 3 && (block == 64 || !cube_order_ok(L, block))) continue;
                 cands.push_back(Shape{block, order, waves});
             }
     }
@@ -900,7 +932,7 @@ int su3hb_batch_create(su3hb_batch **out, int nd, const su3hb_replica_desc *reps
     if (!out) return fail(SU3HB_EINVAL, "out is NULL");
     *out = nullptr;
     if (!reps || n < 1) return fail(SU3HB_EINVAL, "need at least one replica");
-    if (precision < 0 || precision > 2) return fail(SU3HB_EINVAL, "unknown precision %d", precision);
+    if (precision < 0 || precision > 3) return fail(SU3HB_EINVAL, "unknown precision %d", precision);
     double links = 0;
     for (int r = 0; r < n; ++r) {
         uint64_t V;

@@ -228,6 +228,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
+// sin(pi x), cos(pi x) in the precision of x
+__device__ __forceinline__ void sincos_pi(double x, double *s, double *c) { sincospi(x, s, c); }
+__device__ __forceinline__ void sincos_pi(float x, float *s, float *c) { sincospif(x, s, c); }
+
 // 32-bit word -> uniform double (r + 1) / 2^32 in (0, 1]
 __device__ __forceinline__ double u01(uint32_t r) { return (double(r) + 1.0) * 0x1p-32; }
 
@@ -235,9 +239,13 @@ constexpr uint32_t kTagUpdate = 0;
 constexpr uint32_t kTagStart = 1;
 
 // ---------------------------------------------------------------------------
-// Link storage: per replica [layer][mu][parity][element][Vh] with one complex
-// element per entry (double2 or float2), so each element of a matrix is a
-// contiguous, fully coalesced array over the half-lattice index h.
+// Link storage.  Per replica the links form slabs [layer][mu][parity], each
+// holding the Vh links of one direction and parity as structure-of-arrays
+// over the half-lattice index h, so a wave reads consecutive h contiguously:
+//   FP64: one double2 (one complex element) per array, NE arrays;
+//   FP32: elements paired into float4 arrays (2 complex per 16-byte load),
+//         plus one float2 array for the odd element of 18-real storage.
+// Every access goes through a LinkRef (slab base, h).
 
 template <int PREC>
 struct Store;
@@ -245,54 +253,94 @@ struct Store;
 template <>
 struct Store<kFP64_18> {
     using real = double;
-    using elem = double2;
     static constexpr int NE = 9;
 };
 template <>
 struct Store<kFP32_18> {
     using real = float;
-    using elem = float2;
     static constexpr int NE = 9;
 };
 template <>
 struct Store<kFP32_12> {
     using real = float;
-    using elem = float2;
+    static constexpr int NE = 6;
+};
+template <>
+struct Store<kFP64_12> {
+    using real = double;
     static constexpr int NE = 6;
 };
 
+struct LinkRef {
+    char *slab;   // first byte of the (layer, direction, parity) slab
+    uint32_t h;   // half-lattice index of the link
+};
+
+// complex element e of a link
 template <int PREC>
-__device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(
-    const typename Store<PREC>::elem *__restrict__ p, uint32_t Vh)
+__device__ __forceinline__ cx<typename Store<PREC>::real> load_elem(const LinkRef &r, uint32_t Vh, int e)
 {
     using R = typename Store<PREC>::real;
-    mat3<R> m;
+    if constexpr (sizeof(R) == 8) {
+        const double2 v = *reinterpret_cast<const double2 *>(r.slab + (size_t(e) * Vh + r.h) * 16);
+        return cx<R>{v.x, v.y};
+    } else {
+        constexpr int NP = Store<PREC>::NE / 2;
+        if (e >= 2 * NP) {
+            const float2 v = *reinterpret_cast<const float2 *>(r.slab + size_t(NP) * Vh * 16 + size_t(r.h) * 8);
+            return cx<R>{v.x, v.y};
+        }
+        const float2 v = *reinterpret_cast<const float2 *>(r.slab + (size_t(e >> 1) * Vh + r.h) * 16 + (e & 1) * 8);
+        return cx<R>{v.x, v.y};
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const LinkRef &r, uint32_t Vh)
+{
+    using R = typename Store<PREC>::real;
     constexpr int NE = Store<PREC>::NE;
+    mat3<R> m;
+    if constexpr (sizeof(R) == 8) {
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-        const auto v = p[(size_t)e * Vh];
-        m.e[e / 3][e % 3] = cx<R>{v.x, v.y};
+        for (int e = 0; e < NE; ++e) m.e[e / 3][e % 3] = load_elem<PREC>(r, Vh, e);
+    } else {
+        constexpr int NP = NE / 2;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const float4 v = *reinterpret_cast<const float4 *>(r.slab + (size_t(j) * Vh + r.h) * 16);
+            m.e[(2 * j) / 3][(2 * j) % 3] = cx<R>{v.x, v.y};
+            m.e[(2 * j + 1) / 3][(2 * j + 1) % 3] = cx<R>{v.z, v.w};
+        }
+        if constexpr (NE & 1) m.e[2][2] = load_elem<PREC>(r, Vh, NE - 1);
     }
     if constexpr (NE == 6) third_row(m);
     return m;
 }
 
 template <int PREC>
-__device__ __forceinline__ void store_link(typename Store<PREC>::elem *__restrict__ p, uint32_t Vh,
-                                           const mat3<double> &m)
+__device__ __forceinline__ void store_link(const LinkRef &r, uint32_t Vh, const mat3<double> &m)
 {
-    using E = typename Store<PREC>::elem;
     using R = typename Store<PREC>::real;
     constexpr int NE = Store<PREC>::NE;
+    if constexpr (sizeof(R) == 8) {
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-        E v;
-        v.x = R(m.e[e / 3][e % 3].re);
-        v.y = R(m.e[e / 3][e % 3].im);
-        p[(size_t)e * Vh] = v;
+        for (int e = 0; e < NE; ++e)
+            *reinterpret_cast<double2 *>(r.slab + (size_t(e) * Vh + r.h) * 16) =
+                make_double2(m.e[e / 3][e % 3].re, m.e[e / 3][e % 3].im);
+    } else {
+        constexpr int NP = NE / 2;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const cx<double> a = m.e[(2 * j) / 3][(2 * j) % 3], b = m.e[(2 * j + 1) / 3][(2 * j + 1) % 3];
+            *reinterpret_cast<float4 *>(r.slab + (size_t(j) * Vh + r.h) * 16) =
+                make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+        }
+        if constexpr (NE & 1)
+            *reinterpret_cast<float2 *>(r.slab + size_t(NP) * Vh * 16 + size_t(r.h) * 8) =
+                make_float2(float(m.e[2][2].re), float(m.e[2][2].im));
     }
 }
-
 
 // The FP64 matrix a link reads back as after store_link<PREC>(m): rounded to
 // the storage precision, with row 2 rebuilt for 12-real storage.
@@ -313,53 +361,23 @@ __device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
     }
 }
 
-// Row i of a stored link (12-real storage: row 2 is rebuilt from rows 0, 1).
+// acc += w * u1 u2^dag u3^dag.  FP64-18 streams u1 row by row (u2, u3 held
+// whole) to keep registers down; other modes load u1 whole.
 template <int PREC>
-__device__ __forceinline__ void load_link_row(const typename Store<PREC>::elem *__restrict__ p, uint32_t Vh, int i,
-                                              cx<typename Store<PREC>::real> r[3])
-{
-    using R = typename Store<PREC>::real;
-    if (Store<PREC>::NE == 6 && i == 2) {
-        cx<R> a[3], b[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const auto v = p[size_t(c) * Vh];
-            const auto w = p[size_t(3 + c) * Vh];
-            a[c] = cx<R>{v.x, v.y};
-            b[c] = cx<R>{w.x, w.y};
-        }
-        cx<R> c0{R(0), R(0)}, c1{R(0), R(0)}, c2{R(0), R(0)};
-        cfma(c0, a[1], b[2]);
-        cfma(c0, cx<R>{-a[2].re, -a[2].im}, b[1]);
-        cfma(c1, a[2], b[0]);
-        cfma(c1, cx<R>{-a[0].re, -a[0].im}, b[2]);
-        cfma(c2, a[0], b[1]);
-        cfma(c2, cx<R>{-a[1].re, -a[1].im}, b[0]);
-        r[0] = cx<R>{c0.re, -c0.im};
-        r[1] = cx<R>{c1.re, -c1.im};
-        r[2] = cx<R>{c2.re, -c2.im};
-    } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const auto v = p[size_t(3 * i + c) * Vh];
-            r[c] = cx<R>{v.x, v.y};
-        }
-    }
-}
-
-// acc += w * u1 u2^dag u3^dag, streaming u1 row by row (u2, u3 held whole).
-template <int PREC>
-__device__ __forceinline__ void acc_forward_staple(mat3<typename Store<PREC>::real> &acc,
-                                                   const typename Store<PREC>::elem *__restrict__ p1,
+__device__ __forceinline__ void acc_forward_staple(mat3<typename Store<PREC>::real> &acc, const LinkRef &p1,
                                                    const mat3<typename Store<PREC>::real> &u2,
                                                    const mat3<typename Store<PREC>::real> &u3,
                                                    uint32_t Vh, typename Store<PREC>::real w)
 {
     using R = typename Store<PREC>::real;
+    constexpr bool stream = PREC == kFP64_18;
+    mat3<R> m1;
+    if constexpr (!stream) m1 = load_link<PREC>(p1, Vh);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         cx<R> r1[3];
-        load_link_row<PREC>(p1, Vh, i, r1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r1[c] = stream ? load_elem<PREC>(p1, Vh, 3 * i + c) : m1.e[i][c];
         cx<R> t[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -375,21 +393,28 @@ __device__ __forceinline__ void acc_forward_staple(mat3<typename Store<PREC>::re
     }
 }
 
-// acc += w * (u1 u2)^dag u3, streaming rows of u1 and u3 together (u2 whole):
-// (t^dag u3)_ij = sum_k conj(t_ki) u3_kj with t_k. = u1_k. u2.
+// acc += w * (u1 u2)^dag u3 with (t^dag u3)_ij = sum_k conj(t_ki) u3_kj and
+// t_k. = u1_k. u2.  FP64-18 streams rows of u1 and u3 together (u2 whole).
 template <int PREC>
-__device__ __forceinline__ void acc_backward_staple(mat3<typename Store<PREC>::real> &acc,
-                                                    const typename Store<PREC>::elem *__restrict__ p1,
-                                                    const mat3<typename Store<PREC>::real> &u2,
-                                                    const typename Store<PREC>::elem *__restrict__ p3,
+__device__ __forceinline__ void acc_backward_staple(mat3<typename Store<PREC>::real> &acc, const LinkRef &p1,
+                                                    const mat3<typename Store<PREC>::real> &u2, const LinkRef &p3,
                                                     uint32_t Vh, typename Store<PREC>::real w)
 {
     using R = typename Store<PREC>::real;
+    constexpr bool stream = PREC == kFP64_18;
+    mat3<R> m1, m3;
+    if constexpr (!stream) {
+        m1 = load_link<PREC>(p1, Vh);
+        m3 = load_link<PREC>(p3, Vh);
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         cx<R> r1[3], r3[3];
-        load_link_row<PREC>(p1, Vh, k, r1);
-        load_link_row<PREC>(p3, Vh, k, r3);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r1[c] = stream ? load_elem<PREC>(p1, Vh, 3 * k + c) : m1.e[k][c];
+            r3[c] = stream ? load_elem<PREC>(p3, Vh, 3 * k + c) : m3.e[k][c];
+        }
         cx<R> t[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {

@@ -79,17 +79,16 @@ __device__ __forceinline__ Step step_bwd(const RepDesc &rep, const Site<D> &x, i
     return st;
 }
 
-// Pointer to element 0 of link (layer, dir) at the site with number s and
-// parity par; elements follow at stride Vh.
+// Reference to link (layer, dir) at the site with number s and parity par:
+// its slab and its half-lattice index s / 2.
 template <int D, int PREC>
-__device__ __forceinline__ typename Store<PREC>::elem *link_ptr(void *links, const RepDesc &rep,
-                                                                 uint32_t layer, int dir, int par,
-                                                                 uint32_t s)
+__device__ __forceinline__ LinkRef link_ref(void *links, const RepDesc &rep, uint32_t layer, int dir, int par,
+                                            uint32_t s)
 {
-    using E = typename Store<PREC>::elem;
+    constexpr size_t kElemBytes = sizeof(typename Store<PREC>::real) * 2;
     constexpr int NE = Store<PREC>::NE;
     const size_t slab = size_t((layer * D + uint32_t(dir)) * 2u + uint32_t(par)) * NE * rep.Vh;
-    return reinterpret_cast<E *>(links) + rep.elem_offset + slab + (s >> 1);
+    return LinkRef{reinterpret_cast<char *>(links) + (rep.elem_offset + slab) * kElemBytes, s >> 1};
 }
 
 }  // namespace su3hb

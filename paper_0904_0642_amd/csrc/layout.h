@@ -10,12 +10,14 @@ namespace su3hb {
 constexpr int kFP64_18 = 0;
 constexpr int kFP32_18 = 1;
 constexpr int kFP32_12 = 2;
+constexpr int kFP64_12 = 3;
 
 constexpr int kMaxD = 6;          // kernels are instantiated for D = 2 .. 6
 constexpr int kStatSlots = 256;   // spread of the per-block statistics atomics
 
-inline constexpr int elems_per_link(int prec) { return prec == kFP32_12 ? 6 : 9; }
-inline constexpr int bytes_per_elem(int prec) { return prec == kFP64_18 ? 16 : 8; }
+inline constexpr int elems_per_link(int prec) { return (prec == kFP32_12 || prec == kFP64_12) ? 6 : 9; }
+inline constexpr int bytes_per_elem(int prec) { return (prec == kFP64_18 || prec == kFP64_12) ? 16 : 8; }
+inline constexpr bool is_fp32(int prec) { return prec == kFP32_18 || prec == kFP32_12; }
 inline constexpr int bytes_per_link(int prec) { return elems_per_link(prec) * bytes_per_elem(prec); }
 
 // One lattice ("replica").  A single lattice is a batch of one.  Its links
@@ -55,10 +57,12 @@ struct UpdateArgs {
     int mu;                      // direction being updated
     int nhit;                    // KP proposals per subgroup, at most
     int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
-    int order;                   // block order: 0 hardware, 1 XCD-contiguous, 2 XCD slabs
-    uint32_t slab;               // order 2: extent of the last direction per XCD
-    uint32_t cp;                 // order 2: blocks per (x_{D-2}, x_{D-1}) plane
-    uint32_t n2;                 // order 2: extent of direction D-2
+    int order;                   // 0 hardware, 1 XCD-contiguous, 2 XCD slabs, 3 XCD slabs of 3D blocks
+    uint32_t slab;               // orders 2, 3: tiles of the last direction per XCD
+    uint32_t cp;                 // orders 2, 3: blocks (order 3: waves) per (x_{D-2}, x_{D-1}) plane
+    uint32_t n2;                 // orders 2, 3: extent of direction D-2
+    uint32_t plane;              // order 3: half-sites of one (x_{D-2}, x_{D-1}) plane
+    uint32_t tile2, tile3;       // order 3: waves of a block along x_{D-2} and x_{D-1}
     double beta0, beta1;
     const uint32_t *sweep;       // device sweep counter
     StatSlot *stats;             // kStatSlots slots
@@ -76,6 +80,6 @@ struct PlaqArgs {
     uint32_t total_blocks;
 };
 
-constexpr int kDefaultWaves = 2;  // update kernels for D = 4 also exist for 3 waves/SIMD
+constexpr int kDefaultWaves = 2;  // update kernels for D = 4 also exist for 3 (and, FP32, 4) waves/SIMD
 
 }  // namespace su3hb

@@ -16,17 +16,19 @@
 
 namespace su3hb {
 
-// One SU(2)-subgroup heatbath on rows (I, J) of U (and W = U A).
-template <int I, int J, int SUB>
-__device__ __forceinline__ void su2_heatbath(mat3<double> &U, mat3<double> &W, uint32_t lid,
-                                             uint32_t sweep, int nhit, uint32_t k0, uint32_t k1,
-                                             int &attempts, int &accepts)
+// One SU(2)-subgroup heatbath on rows (I, J) of U (and W = U A), with U, W
+// and the rotation in H (double for FP64 storage, float for FP32 storage).
+// The norm k, alpha and the Kennedy-Pendleton draw and acceptance test are
+// FP64 in every mode.
+template <typename H, int I, int J, int SUB>
+__device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t lid, uint32_t sweep, int nhit,
+                                             uint32_t k0, uint32_t k1, int &attempts, int &accepts)
 {
     // quaternion part a0 + i a.sigma of the 2x2 block (I, J) of W
-    const double a0 = 0.5 * (W.e[I][I].re + W.e[J][J].re);
-    const double a1 = 0.5 * (W.e[I][J].im + W.e[J][I].im);
-    const double a2 = 0.5 * (W.e[I][J].re - W.e[J][I].re);
-    const double a3 = 0.5 * (W.e[I][I].im - W.e[J][J].im);
+    const double a0 = 0.5 * (double(W.e[I][I].re) + double(W.e[J][J].re));
+    const double a1 = 0.5 * (double(W.e[I][J].im) + double(W.e[J][I].im));
+    const double a2 = 0.5 * (double(W.e[I][J].re) - double(W.e[J][I].re));
+    const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
     const double k = sqrt(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))));
     if (!(k > 1e-300)) return;  // degenerate projection: every hit rejected
     const double alpha = 2.0 * k / 3.0;
@@ -50,25 +52,27 @@ __device__ __forceinline__ void su2_heatbath(mat3<double> &U, mat3<double> &W, u
     }
     if (!ok) return;
     ++accepts;
-    const double x0 = 1.0 - delta;
+    const double x0d = 1.0 - delta;
 
     // (x1, x2, x3) uniform on the sphere of radius sqrt(1 - x0^2)
     const uint4 q = philox4x32_10(
         make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1) | 1u, kTagUpdate), k0, k1);
-    const double rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
-    const double cth = 2.0 * u01(q.x) - 1.0;
-    const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
-    double sph, cph;
-    sincospi(2.0 * u01(q.y), &sph, &cph);  // phi = 2 pi u
-    const double x1 = rad * sth * cph, x2 = rad * sth * sph, x3 = rad * cth;
+    const H x0 = H(x0d);
+    const H rad = H(sqrt(fmax(0.0, 1.0 - x0d * x0d)));
+    const H cth = H(2.0 * u01(q.x) - 1.0);
+    const H sth = sqrt(max(H(0), H(1) - cth * cth));
+    H sph, cph;
+    sincos_pi(H(2.0 * u01(q.y)), &sph, &cph);  // phi = 2 pi u
+    const H x1 = rad * sth * cph, x2 = rad * sth * sph, x3 = rad * cth;
 
     // r = X V^dag, X = [[x0 + i x3, x2 + i x1], [-x2 + i x1, x0 - i x3]],
     // V^dag = [[a0 - i a3, -a2 - i a1], [a2 - i a1, a0 + i a3]] / k
     const double ik = 1.0 / k;
-    const cx<double> X00{x0, x3}, X01{x2, x1}, X10{-x2, x1}, X11{x0, -x3};
-    const cx<double> V00{a0 * ik, -a3 * ik}, V01{-a2 * ik, -a1 * ik}, V10{a2 * ik, -a1 * ik},
-        V11{a0 * ik, a3 * ik};
-    cx<double> r00{0, 0}, r01{0, 0}, r10{0, 0}, r11{0, 0};
+    const H b0 = H(a0 * ik), b1 = H(a1 * ik), b2 = H(a2 * ik), b3 = H(a3 * ik);
+    const cx<H> X00{x0, x3}, X01{x2, x1}, X10{-x2, x1}, X11{x0, -x3};
+    const cx<H> V00{b0, -b3}, V01{-b2, -b1}, V10{b2, -b1}, V11{b0, b3};
+    const H z = H(0);
+    cx<H> r00{z, z}, r01{z, z}, r10{z, z}, r11{z, z};
     cfma(r00, X00, V00); cfma(r00, X01, V10);
     cfma(r01, X00, V01); cfma(r01, X01, V11);
     cfma(r10, X10, V00); cfma(r10, X11, V10);
@@ -77,14 +81,14 @@ __device__ __forceinline__ void su2_heatbath(mat3<double> &U, mat3<double> &W, u
     // U <- R_IJ(r) U and W <- R_IJ(r) W (rows I and J)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const cx<double> ui = U.e[I][c], uj = U.e[J][c];
-        cx<double> ni{0, 0}, nj{0, 0};
+        const cx<H> ui = U.e[I][c], uj = U.e[J][c];
+        cx<H> ni{z, z}, nj{z, z};
         cfma(ni, r00, ui); cfma(ni, r01, uj);
         cfma(nj, r10, ui); cfma(nj, r11, uj);
         U.e[I][c] = ni;
         U.e[J][c] = nj;
-        const cx<double> wi = W.e[I][c], wj = W.e[J][c];
-        cx<double> mi{0, 0}, mj{0, 0};
+        const cx<H> wi = W.e[I][c], wj = W.e[J][c];
+        cx<H> mi{z, z}, mj{z, z};
         cfma(mi, r00, wi); cfma(mi, r01, wj);
         cfma(mj, r10, wi); cfma(mj, r11, wj);
         W.e[I][c] = mi;
@@ -146,36 +150,39 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
         // forward staple: U_nu(x+mu) streamed by rows
         {
             const uint32_t tags = layer + l_pm + l_pn + layer;
-            const mat3<R> u2 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, l_pn, mu, q, s_pn), Vh);
-            const mat3<R> u3 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, layer, nu, p, x.s), Vh);
-            acc_forward_staple<PREC>(A, link_ptr<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), u2, u3, Vh,
+            const mat3<R> u2 = load_link<PREC>(link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn), Vh);
+            const mat3<R> u3 = load_link<PREC>(link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s), Vh);
+            acc_forward_staple<PREC>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), u2, u3, Vh,
                                      single ? R(1) : R(tags == 0 ? beta0 : beta1));
         }
         // backward staple: U_mu(x-nu) and U_nu(x-nu) streamed by rows
         {
             const uint32_t tags = l_mn + l_pmmn + layer + l_mn;
-            const mat3<R> u2 = load_link<PREC>(link_ptr<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), Vh);
-            acc_backward_staple<PREC>(A, link_ptr<D, PREC>(a.links, rep, l_mn, mu, q, s_mn), u2,
-                                      link_ptr<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
+            const mat3<R> u2 = load_link<PREC>(link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), Vh);
+            acc_backward_staple<PREC>(A, link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn), u2,
+                                      link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
                                       single ? R(1) : R(tags == 0 ? beta0 : beta1));
         }
     }
     if (single) scale(A, R(beta0));
 
-    auto *uptr = link_ptr<D, PREC>(a.links, rep, layer, mu, p, x.s);
-    mat3<double> U = widen<double>(load_link<PREC>(uptr, Vh));
-    mat3<double> W = mul_nn(U, widen<double>(A));   // A is not needed past this point
-    const double tr_old = W.e[0][0].re + W.e[1][1].re + W.e[2][2].re;
+    // heatbath in the storage precision (FP64 for the draw, see su2_heatbath)
+    const LinkRef uptr = link_ref<D, PREC>(a.links, rep, layer, mu, p, x.s);
+    mat3<R> U = load_link<PREC>(uptr, Vh);
+    mat3<R> W = mul_nn(U, A);   // A is not needed past this point (except Alow)
+    const double tr_old = double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 
     const uint32_t lid = ((rep.lat2test ? 0u : layer * rep.V) + x.s) * uint32_t(D) + uint32_t(mu);
-    su2_heatbath<0, 1, 0>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[0], acc[0]);
-    su2_heatbath<0, 2, 1>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[1], acc[1]);
-    su2_heatbath<1, 2, 2>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[2], acc[2]);
+    su2_heatbath<R, 0, 1, 0>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[0], acc[0]);
+    su2_heatbath<R, 0, 2, 1>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[1], acc[1]);
+    su2_heatbath<R, 1, 2, 2>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[2], acc[2]);
     // W was rotated with U, so Re Tr W is now Re Tr(U' A)
-    dtrace += (W.e[0][0].re + W.e[1][1].re + W.e[2][2].re - tr_old) * (1.0 / 3.0);
-    reunitarize(U);
-    if (measure) plaq = re_tr_nn(stored_form<PREC>(U), widen<double>(Alow)) * (1.0 / 3.0);
-    store_link<PREC>(uptr, Vh, U);
+    dtrace += (double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re) - tr_old) * (1.0 / 3.0);
+    // reunitarisation in FP64 in every mode
+    mat3<double> Ud = widen<double>(U);
+    reunitarize(Ud);
+    if (measure) plaq = re_tr_nn(stored_form<PREC>(Ud), widen<double>(Alow)) * (1.0 / 3.0);
+    store_link<PREC>(uptr, Vh, Ud);
 }
 
 // Sum the per-thread counters over the block and add them to one slot; with
@@ -224,16 +231,19 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
     __syncthreads();  // the shared arrays are reused by the next block in a persistent loop
 }
 
-// Update the links of logical block lb (replica found by binary search).
+// Update the links of logical block lb (replica found by binary search);
+// lt_override >= 0 gives the thread's link directly (order 3).
 template <int D, int PREC>
-__device__ __forceinline__ void process_block(const UpdateArgs &a, uint32_t lb, uint32_t sweep)
+__device__ __forceinline__ void process_block(const UpdateArgs &a, uint32_t lb, uint32_t sweep,
+                                              int64_t lt_override = -1)
 {
     int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
     double dtrace = 0.0, plaq = 0.0;
     if (lb < a.total_blocks) {
         const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, false);
         const RepDesc &rep = a.reps[r];
-        const uint32_t lt = (lb - rep.upd_block0) * blockDim.x + threadIdx.x;
+        const uint32_t lt = lt_override >= 0 ? uint32_t(lt_override)
+                                             : (lb - rep.upd_block0) * blockDim.x + threadIdx.x;
         if (lt < rep.nlat * rep.Vh) {
             update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
             upd = 1;
@@ -260,13 +270,41 @@ __device__ __forceinline__ uint32_t logical_block(const UpdateArgs &a, uint32_t 
         const uint32_t c = t % a.cp, x2 = t / a.cp;
         return (x2 + a.n2 * (k * a.slab + xl)) * a.cp + c;
     }
+    if (a.order == 4) {
+        // as order 2 with the block's chunk of the plane slowest and x_{D-2}
+        // in the middle: neighbours along x_{D-2} are one slab apart
+        const uint32_t k = b & 7u, e = b >> 3;
+        const uint32_t xl = e % a.slab, t = e / a.slab;
+        const uint32_t x2 = t % a.n2, c = t / a.n2;
+        return (x2 + a.n2 * (k * a.slab + xl)) * a.cp + c;
+    }
     return b;
+}
+
+// Order 3: a block is tile2 x tile3 waves stacked along x_{D-2} and x_{D-1},
+// each wave 64 consecutive half-sites of its (x_{D-2}, x_{D-1}) plane, so the
+// neighbours along the two slowest directions are loaded by sibling waves at
+// nearly the same time.  Blocks walk XCD slabs as in order 2.  Returns the
+// half-lattice index of the calling thread's link.
+__device__ __forceinline__ uint32_t link_of_thread_3d(const UpdateArgs &a, uint32_t b)
+{
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint32_t w2 = w % a.tile2, w3 = w / a.tile2;
+    const uint32_t k = b & 7u, e = b >> 3;
+    const uint32_t xl = e % a.slab, t = e / a.slab;
+    const uint32_t c = t % a.cp, x2t = t / a.cp;
+    const uint32_t x2 = x2t * a.tile2 + w2;
+    const uint32_t x3 = (k * a.slab + xl) * a.tile3 + w3;
+    return (x2 + a.n2 * x3) * a.plane + c * 64u + lane;
 }
 
 template <int D, int PREC, int WAVES>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
-    process_block<D, PREC>(a, logical_block(a, blockIdx.x), *a.sweep);
+    if (a.order == 3)
+        process_block<D, PREC>(a, blockIdx.x, *a.sweep, int64_t(link_of_thread_3d(a, blockIdx.x)));
+    else
+        process_block<D, PREC>(a, logical_block(a, blockIdx.x), *a.sweep);
 }
 
 // Persistent form for batches: the grid stays resident for n_sweeps sweeps,
@@ -296,13 +334,19 @@ __global__ void __launch_bounds__(256) update_persistent_kernel(UpdateArgs a, in
 template <int D, int PREC>
 static hipError_t launch_update_t(int waves, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
 {
-    if (waves == 3) {
-        if constexpr (D == 4) {
+    if constexpr (D == 4) {
+        if (waves == 3) {
             hipLaunchKernelGGL((update_kernel<D, PREC, 3>), grid, block, 0, st, a);
             return hipGetLastError();
         }
-        return hipErrorInvalidValue;
+        if constexpr (PREC == kFP32_18 || PREC == kFP32_12) {
+            if (waves == 4) {
+                hipLaunchKernelGGL((update_kernel<D, PREC, 4>), grid, block, 0, st, a);
+                return hipGetLastError();
+            }
+        }
     }
+    if (waves != kDefaultWaves) return hipErrorInvalidValue;
     hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves>), grid, block, 0, st, a);
     return hipGetLastError();
 }
@@ -315,6 +359,7 @@ static hipError_t launch_update_d(int prec, int waves, dim3 grid, dim3 block, hi
     case kFP64_18: return launch_update_t<D, kFP64_18>(waves, grid, block, st, a);
     case kFP32_18: return launch_update_t<D, kFP32_18>(waves, grid, block, st, a);
     case kFP32_12: return launch_update_t<D, kFP32_12>(waves, grid, block, st, a);
+    case kFP64_12: return launch_update_t<D, kFP64_12>(waves, grid, block, st, a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -333,6 +378,7 @@ static const void *persistent_fn(int D, int prec)
         case kFP64_18: return persistent_fn<DD, kFP64_18>();          \
         case kFP32_18: return persistent_fn<DD, kFP32_18>();          \
         case kFP32_12: return persistent_fn<DD, kFP32_12>();          \
+        case kFP64_12: return persistent_fn<DD, kFP64_12>();          \
         default: return nullptr;                                      \
         }
     switch (D) {

@@ -20,7 +20,8 @@ import numpy as np
 FP64_18 = 0
 FP32_18 = 1
 FP32_12 = 2
-PRECISION_NAMES = {FP64_18: "fp64-18", FP32_18: "fp32-18", FP32_12: "fp32-12"}
+FP64_12 = 3
+PRECISION_NAMES = {FP64_18: "fp64-18", FP32_18: "fp32-18", FP32_12: "fp32-12", FP64_12: "fp64-12"}
 COLD = 1
 HOT = 2
 

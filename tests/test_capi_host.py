@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_links_bytes():
-    for prec, b in ((su3hb.FP64_18, 144), (su3hb.FP32_18, 72), (su3hb.FP32_12, 48)):
+    for prec, b in ((su3hb.FP64_18, 144), (su3hb.FP32_18, 72), (su3hb.FP32_12, 48), (su3hb.FP64_12, 96)):
         p = su3hb.make_params([4, 4, 4, 4], precision=prec)
         assert su3hb.su3hb_links_bytes(p) == 256 * 4 * b
     p = su3hb.make_params([24, 24, 24, 8], nlat=2, dlt_mask=15, precision=su3hb.FP32_18)

@@ -160,6 +160,22 @@ def test_fp32_storage_one_sweep(oracle_mod, prec):
     assert unit < 1e-6
 
 
+@pytest.mark.parametrize("ext", [[8, 8, 8, 4], [6, 4, 2, 10], [16, 8]])
+def test_fp64_12_storage_matches_oracle(oracle_mod, ext):
+    # 12-real FP64 storage rebuilds row 2 = conj(row0 x row1) on load: the same
+    # SU(3) matrix to rounding, so the FP64 bound holds
+    g, o = pair(oracle_mod, ext, prec=su3hb.FP64_12, seed=23)
+    assert maxdiff(g.get_links(), o.get_links()) <= 1e-12
+    for _ in range(2):
+        g.sweep(5.8, n_hit=8, n_sweeps=1)
+        o.sweep(5.8, nhit=8, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  fp64-12 {ext}: max |dU| after 2 sweeps = {d:.3e}")
+    assert d <= TOL64
+    pg, po = g.plaquette(5.8), o.plaquette(5.8)
+    assert np.allclose(pg, po, rtol=1e-12, atol=0, equal_nan=True)
+
+
 def test_plaquette_of_same_links(oracle_mod):
     g, o = pair(oracle_mod, [8, 4, 6, 4], seed=13)
     o.sweep(5.9, nhit=2, nsweeps=1)
@@ -215,17 +231,19 @@ def test_resume_is_bitwise(oracle_mod):
 
 
 @pytest.mark.parametrize("prec,ext", [(su3hb.FP64_18, [12, 6, 4, 8]), (su3hb.FP32_12, [12, 6, 4, 8]),
-                                      (su3hb.FP32_18, [8, 4, 8, 16])])
+                                      (su3hb.FP32_18, [8, 4, 8, 16]), (su3hb.FP64_18, [16, 8, 4, 16]),
+                                      (su3hb.FP64_12, [16, 8, 4, 16])])
 def test_launch_shape_invariance(prec, ext):
     # every block size, block order and occupancy target gives the same links
     ref = None
-    for waves in (2, 3):
+    fp32 = prec in (su3hb.FP32_18, su3hb.FP32_12)
+    for waves in ((2, 3, 4) if fp32 else (2, 3)):
         for block in (64, 128, 256):
-            for order in (0, 1, 2):
+            for order in (0, 1, 2, 3, 4):
                 g = su3hb.Lattice(ext, seed=8, precision=prec)
                 g.set_launch(block, order, waves)
                 b, o, w = g.get_launch()
-                assert (b, w) == (block, waves) and o in (order, 1)
+                assert (b, w) == (block, waves) and (o == order or o in (1, 2))
                 g.sweep(6.1, n_hit=8, n_sweeps=2)
                 links = g.get_links()
                 if ref is None:
@@ -233,8 +251,11 @@ def test_launch_shape_invariance(prec, ext):
                 assert np.array_equal(links, ref), (block, order, waves)
     with pytest.raises(su3hb.SU3HBError):
         g.set_launch(96, 0, 2)
+    if not fp32:
+        with pytest.raises(su3hb.SU3HBError):
+            g.set_launch(64, 0, 4)
     with pytest.raises(su3hb.SU3HBError):
-        g.set_launch(64, 3, 2)
+        g.set_launch(64, 5, 2)
 
 
 def test_graph_replay_equals_direct_launches():
@@ -280,6 +301,7 @@ def test_batch_replica_equals_single(prec):
 
 
 @pytest.mark.parametrize("ext,prec,tol", [([8, 8, 8, 8], su3hb.FP64_18, 1e-13), ([6, 4, 8], su3hb.FP64_18, 1e-13),
+                                          ([8, 8, 8, 8], su3hb.FP64_12, 1e-13),
                                           ([16, 8], su3hb.FP64_18, 1e-13), ([4, 4, 2, 4, 2], su3hb.FP64_18, 1e-13),
                                           ([8, 8, 8, 8], su3hb.FP32_12, 2e-6), ([8, 8, 8, 8], su3hb.FP32_18, 2e-6)])
 def test_fused_measurement_equals_plaquette_kernel(ext, prec, tol):

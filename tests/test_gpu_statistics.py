@@ -147,12 +147,12 @@ def test_fp32_vs_fp64_same_plaquette():
     # FP32 link storage (FP64 heatbath, reunitarisation, accumulation) gives
     # the same <P> as FP64 within the statistical error of equal-length runs
     res = {}
-    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
+    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
         lat = su3hb.Lattice([16, 16, 16, 16], seed=10, precision=prec)
         s = run_series(lat, 6.0, ntherm=300, nmeas=3000)
         res[prec] = jackknife_mean(s, 32)
     (m64, e64) = res[su3hb.FP64_18]
-    for prec in (su3hb.FP32_18, su3hb.FP32_12):
+    for prec in (su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
         m, e = res[prec]
         say(f"  16^4 beta=6.0 prec={prec}: {m:.6f}({e*1e6:.0f}) vs FP64 {m64:.6f}({e64*1e6:.0f})")
         assert abs(m - m64) < 3 * np.hypot(e, e64)
