@@ -988,12 +988,12 @@ int su3hb_batch_sweep(su3hb_batch *L, int n_hit, int n_sweeps, int mode, su3hb_s
         if (rc) return rc;
     } else if (n_sweeps > 0) {
         int per_cu = 0;
-        HIPCHK(persistent_max_blocks(L->nd, L->prec, L->block, &per_cu));
+        HIPCHK(persistent_max_blocks(L->nd, L->prec, L->waves, L->block, &per_cu));
         if (per_cu < 1) return fail(SU3HB_EUNSUPPORTED, "persistent kernel cannot be resident");
         const int blocks = int(std::min<uint64_t>(uint64_t(per_cu) * L->num_cus, L->upd_blocks));
         UpdateArgs a = update_args(L, 0.0, 0.0, n_hit);
         a.order = 0;
-        HIPCHK(launch_update_persistent(L->nd, L->prec, blocks, L->block, L->stream, a, n_sweeps));
+        HIPCHK(launch_update_persistent(L->nd, L->prec, L->waves, blocks, L->block, L->stream, a, n_sweeps));
         HIPCHK(launch_counter_add(L->stream, L->d_sweep, uint32_t(n_sweeps)));
         L->sweep += uint64_t(n_sweeps);
     }

@@ -13,9 +13,9 @@ hipError_t launch_update(int D, int prec, int waves, dim3 grid, dim3 block, hipS
                          const UpdateArgs &a);
 
 // persistent cooperative batch sweep: n_sweeps x 2D slices with a grid barrier
-hipError_t launch_update_persistent(int D, int prec, int blocks, int threads, hipStream_t st,
+hipError_t launch_update_persistent(int D, int prec, int waves, int blocks, int threads, hipStream_t st,
                                     const UpdateArgs &a, int n_sweeps);
-hipError_t persistent_max_blocks(int D, int prec, int threads, int *blocks_per_cu);
+hipError_t persistent_max_blocks(int D, int prec, int waves, int threads, int *blocks_per_cu);
 
 // plaquettes: per-block partial sums, then one block per replica finalises
 hipError_t launch_plaquette(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const PlaqArgs &a);

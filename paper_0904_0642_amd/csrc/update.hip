@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 // between slices (the next slice reads links this one wrote).  The sweep
 // number is the counter's value at entry plus the local sweep index; the
 // counter itself is advanced once, by the host, after the launch.
-template <int D, int PREC>
-__global__ void __launch_bounds__(256) update_persistent_kernel(UpdateArgs a, int n_sweeps)
+template <int D, int PREC, int WAVES>
+__global__ void __launch_bounds__(256, WAVES) update_persistent_kernel(UpdateArgs a, int n_sweeps)
 {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     const uint32_t sweep0 = *a.sweep;
@@ -365,20 +365,26 @@ static hipError_t launch_update_d(int prec, int waves, dim3 grid, dim3 block, hi
 }
 
 template <int D, int PREC>
-static const void *persistent_fn()
+static const void *persistent_fn(int waves)
 {
-    return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC>);
+    if constexpr (D == 4) {
+        if (waves == 3) return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC, 3>);
+        if constexpr (PREC == kFP32_18 || PREC == kFP32_12)
+            if (waves == 4) return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC, 4>);
+    }
+    if (waves != kDefaultWaves) return nullptr;
+    return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC, kDefaultWaves>);
 }
 
-static const void *persistent_fn(int D, int prec)
+static const void *persistent_fn(int D, int prec, int waves)
 {
 #define SU3HB_P(DD)                                                   \
     case DD:                                                          \
         switch (prec) {                                               \
-        case kFP64_18: return persistent_fn<DD, kFP64_18>();          \
-        case kFP32_18: return persistent_fn<DD, kFP32_18>();          \
-        case kFP32_12: return persistent_fn<DD, kFP32_12>();          \
-        case kFP64_12: return persistent_fn<DD, kFP64_12>();          \
+        case kFP64_18: return persistent_fn<DD, kFP64_18>(waves);     \
+        case kFP32_18: return persistent_fn<DD, kFP32_18>(waves);     \
+        case kFP32_12: return persistent_fn<DD, kFP32_12>(waves);     \
+        case kFP64_12: return persistent_fn<DD, kFP64_12>(waves);     \
         default: return nullptr;                                      \
         }
     switch (D) {
@@ -392,17 +398,17 @@ static const void *persistent_fn(int D, int prec)
 #undef SU3HB_P
 }
 
-hipError_t persistent_max_blocks(int D, int prec, int threads, int *blocks_per_cu)
+hipError_t persistent_max_blocks(int D, int prec, int waves, int threads, int *blocks_per_cu)
 {
-    const void *fn = persistent_fn(D, prec);
+    const void *fn = persistent_fn(D, prec, waves);
     if (!fn) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, 0);
 }
 
-hipError_t launch_update_persistent(int D, int prec, int blocks, int threads, hipStream_t st,
+hipError_t launch_update_persistent(int D, int prec, int waves, int blocks, int threads, hipStream_t st,
                                     const UpdateArgs &a, int n_sweeps)
 {
-    const void *fn = persistent_fn(D, prec);
+    const void *fn = persistent_fn(D, prec, waves);
     if (!fn) return hipErrorInvalidValue;
     UpdateArgs args = a;
     int ns = n_sweeps;
