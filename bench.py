@@ -229,26 +229,32 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
     return res
 
 
-def cpu_baseline(name: str, n_hit: int):
-    """The FP64 oracle on a bounded sample of the same workload: the first two
-    checkerboard slices (parity 0, directions 0 and 1) of the hot-started
-    lattice, with OpenMP over the sites of a slice on the host cores."""
+def cpu_baseline(name: str, n_hit: int, min_secs: float = 10.0, max_sweeps: int = 6):
+    """The FP64 oracle on a bounded sample of the same workload: checkerboard
+    slices of the hot-started lattice in sweep order (parity 0, 1; directions
+    0..D-1), with OpenMP over the sites of a slice on the host cores, until
+    min_secs have passed or max_sweeps sweeps are done."""
     import oracle
 
     ext, prec, beta = WORKLOADS[name]
+    D = len(ext)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = oracle.Lattice(list(ext), seed=1, threads=threads)
     o.hot_start()
     V = int(np.prod(ext))
+    slices = 0
     t0 = time.perf_counter()
-    for mu in (0, 1):
-        o.update_slice(0, mu, beta, beta, nhit=n_hit)
+    while slices < 2 * D * max_sweeps:
+        o.update_slice(slices // D % 2, slices % D, beta, beta, nhit=n_hit)
+        slices += 1
+        if time.perf_counter() - t0 >= min_secs:
+            break
     secs = time.perf_counter() - t0
-    n = 2 * (V // 2)
+    n = slices * (V // 2)
     return {"value": n / secs, "unit": "link updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"2 checkerboard slices ({n} link updates) of the hot-started {'x'.join(map(str, ext))} "
-                      f"lattice at beta={beta}, n_hit={n_hit}, FP64 C oracle, OpenMP {threads} threads, "
-                      f"{secs:.2f} s"}
+            "sample": f"{slices} checkerboard slices in sweep order ({n} link updates) of the hot-started "
+                      f"{'x'.join(map(str, ext))} lattice at beta={beta}, n_hit={n_hit}, FP64 C oracle, "
+                      f"OpenMP {threads} threads, {secs:.2f} s"}
 
 
 def main():
@@ -271,7 +277,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the whole lattice is resident on a single MI355X; "
-              "multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+              "runs on more than one GPU are not supported (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -334,6 +340,16 @@ def main():
         line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
         line["dlt_2x24^3x8_fp32"] = dlt_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
         line["precision_study"] = precision_study(args.n_hit)
+        for name in ("64^4-fp32-18", "48^4-fp64-12"):
+            if name in (args.workload, args.compare):
+                continue
+            leg = run_leg(name, args.steps, args.warmup, args.n_hit, args.autotune_ms)
+            line["full_size_" + name] = {
+                "value": round(leg["rate"], 1), "unit": "link updates/s",
+                "ms_per_step": round(leg["ms_per_step"], 4), "roofline": leg["roofline"],
+                "update_kernel_ms": round(leg["update_kernel_ms"], 5), "launch": leg["launch"],
+                "rate_ratio_vs_main": round(leg["rate"] / main_leg["rate"], 3),
+            }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.n_hit)
     print(json.dumps(line), flush=True)
