@@ -287,6 +287,7 @@ __device__ __forceinline__ void site_from_number(const RepDesc &rep, uint32_t s,
         sum += x.x[i];
     }
     x.s = s;
+    x.set_edges(rep);
     p = sum & 1;
 }
 

@@ -361,72 +361,87 @@ __device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
     }
 }
 
-// acc += w * u1 u2^dag u3^dag.  FP64-18 streams u1 row by row (u2, u3 held
-// whole) to keep registers down; other modes load u1 whole.
+// Both staples of one plane (nu, mu) at x:
+//   forward  U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag        = F1 (F3 F2)^dag
+//   backward U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)   = (B2 B1)^dag B3
+// acc += wf F1 T + wb S B3 with T = (F3 F2)^dag and S = (B2 B1)^dag.  The
+// loads come in pairs that other threads of the slice read too (F3 of the
+// link at x is B1 of the link at x - mu + nu, F2 of x is B2 of x + 2 nu, F1
+// of x is B3 of x + mu + nu), each pair issued back to back so that the
+// second read of a line finds it still in L2.  FP64-18 streams F2, B2, F1 and
+// B3 row by row to keep registers down; other modes load whole links.
 template <int PREC>
-__device__ __forceinline__ void acc_forward_staple(mat3<typename Store<PREC>::real> &acc, const LinkRef &p1,
-                                                   const mat3<typename Store<PREC>::real> &u2,
-                                                   const mat3<typename Store<PREC>::real> &u3,
-                                                   uint32_t Vh, typename Store<PREC>::real w)
+__device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
+                                                  const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
+                                                  const LinkRef &b2, const LinkRef &b3, uint32_t Vh,
+                                                  typename Store<PREC>::real wf, typename Store<PREC>::real wb)
 {
     using R = typename Store<PREC>::real;
     constexpr bool stream = PREC == kFP64_18;
-    mat3<R> m1;
-    if constexpr (!stream) m1 = load_link<PREC>(p1, Vh);
+    const mat3<R> m3 = load_link<PREC>(f3, Vh);
+    const mat3<R> mb1 = load_link<PREC>(b1, Vh);
+    // T_ij = wf conj(sum_k F3_jk F2_ki): row k of F2 adds to every T_ij
+    mat3<R> T;
+    set_zero(T);
+    {
+        mat3<R> m2;
+        if constexpr (!stream) m2 = load_link<PREC>(f2, Vh);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        cx<R> r1[3];
+        for (int k = 0; k < 3; ++k) {
+            cx<R> r2[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r1[c] = stream ? load_elem<PREC>(p1, Vh, 3 * i + c) : m1.e[i][c];
-        cx<R> t[3];
+            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(f2, Vh, 3 * k + c) : m2.e[k][c];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<R> s{R(0), R(0)};
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) cfma_nc(s, r1[k], u2.e[j][k]);
-            t[j] = cx<R>{w * s.re, w * s.im};
-        }
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cfma_nc(acc.e[i][j], t[k], u3.e[j][k]);
-    }
-}
-
-// acc += w * (u1 u2)^dag u3 with (t^dag u3)_ij = sum_k conj(t_ki) u3_kj and
-// t_k. = u1_k. u2.  FP64-18 streams rows of u1 and u3 together (u2 whole).
-template <int PREC>
-__device__ __forceinline__ void acc_backward_staple(mat3<typename Store<PREC>::real> &acc, const LinkRef &p1,
-                                                    const mat3<typename Store<PREC>::real> &u2, const LinkRef &p3,
-                                                    uint32_t Vh, typename Store<PREC>::real w)
-{
-    using R = typename Store<PREC>::real;
-    constexpr bool stream = PREC == kFP64_18;
-    mat3<R> m1, m3;
-    if constexpr (!stream) {
-        m1 = load_link<PREC>(p1, Vh);
-        m3 = load_link<PREC>(p3, Vh);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        cx<R> r1[3], r3[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            r1[c] = stream ? load_elem<PREC>(p1, Vh, 3 * k + c) : m1.e[k][c];
-            r3[c] = stream ? load_elem<PREC>(p3, Vh, 3 * k + c) : m3.e[k][c];
-        }
-        cx<R> t[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            cx<R> s{R(0), R(0)};
-#pragma unroll
-            for (int m = 0; m < 3; ++m) cfma(s, r1[m], u2.e[m][i]);
-            t[i] = cx<R>{w * s.re, w * s.im};
+                for (int j = 0; j < 3; ++j) cfma_cn(T.e[i][j], m3.e[j][k], cx<R>{r2[i].re, -r2[i].im});
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) cfma_cn(acc.e[i][j], t[i], r3[j]);
+            for (int j = 0; j < 3; ++j) T.e[i][j] = cx<R>{wf * T.e[i][j].re, wf * T.e[i][j].im};
+    }
+    // S_ij = wb conj(sum_k B2_jk B1_ki): row j of B2 gives column j of S
+    mat3<R> S;
+    {
+        mat3<R> mb2;
+        if constexpr (!stream) mb2 = load_link<PREC>(b2, Vh);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<R> r2[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(b2, Vh, 3 * j + c) : mb2.e[j][c];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                cx<R> s{R(0), R(0)};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cfma(s, r2[k], mb1.e[k][i]);
+                S.e[i][j] = cx<R>{wb * s.re, -wb * s.im};
+            }
+        }
+    }
+    // acc += F1 T + S B3, F1 and B3 taken row by row together
+    mat3<R> m1, mb3;
+    if constexpr (!stream) {
+        m1 = load_link<PREC>(f1, Vh);
+        mb3 = load_link<PREC>(b3, Vh);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        cx<R> r1[3], r3[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r1[c] = stream ? load_elem<PREC>(f1, Vh, 3 * r + c) : m1.e[r][c];
+            r3[c] = stream ? load_elem<PREC>(b3, Vh, 3 * r + c) : mb3.e[r][c];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cfma(acc.e[r][j], r1[k], T.e[k][j]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) cfma(acc.e[i][j], S.e[i][r], r3[j]);
     }
 }
 

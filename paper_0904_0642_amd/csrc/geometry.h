@@ -50,6 +50,23 @@ struct Site {
         x[0] = int(2 * hx) + (psum & 1);
         s = 2 * h + uint32_t(psum & 1);
         layer = lay;
+        set_edges(rep);
+    }
+
+    // bit i of hi (lo): x_i is the last (first) coordinate of direction i.
+    // Steps along a run-time direction read these bits instead of indexing
+    // the coordinate array, which would move it to scratch memory.
+    uint32_t hi, lo;
+
+    __device__ __forceinline__ void set_edges(const RepDesc &rep)
+    {
+        hi = 0;
+        lo = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            hi |= uint32_t(x[i] == rep.n[i] - 1) << i;
+            lo |= uint32_t(x[i] == 0) << i;
+        }
     }
 };
 
@@ -62,7 +79,7 @@ struct Step {
 template <int D>
 __device__ __forceinline__ Step step_fwd(const RepDesc &rep, const Site<D> &x, int dir, uint32_t glued)
 {
-    const bool wrap = x.x[dir] == rep.n[dir] - 1;
+    const bool wrap = (x.hi >> dir) & 1u;
     Step st;
     st.ds = wrap ? -int32_t((rep.n[dir] - 1) * rep.stride[dir]) : int32_t(rep.stride[dir]);
     st.flip = wrap ? ((glued >> dir) & 1u) : 0u;
@@ -72,7 +89,7 @@ __device__ __forceinline__ Step step_fwd(const RepDesc &rep, const Site<D> &x, i
 template <int D>
 __device__ __forceinline__ Step step_bwd(const RepDesc &rep, const Site<D> &x, int dir, uint32_t glued)
 {
-    const bool wrap = x.x[dir] == 0;
+    const bool wrap = (x.lo >> dir) & 1u;
     Step st;
     st.ds = wrap ? int32_t((rep.n[dir] - 1) * rep.stride[dir]) : -int32_t(rep.stride[dir]);
     st.flip = wrap ? ((glued >> dir) & 1u) : 0u;

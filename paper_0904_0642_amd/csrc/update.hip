@@ -132,13 +132,19 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     //                             + beta_b U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
     const Step fm = step_fwd<D>(rep, x, mu, glued);
     const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
-    mat3<R> A, Alow;
+    // the unweighted sum of the planes nu < mu waits in this thread's slot of
+    // dynamic LDS (element-major, sized by the launch when measuring)
+    extern __shared__ char s_dyn[];
+    cx<R> *alow = reinterpret_cast<cx<R> *>(s_dyn);
+    mat3<R> A;
     set_zero(A);
-    set_zero(Alow);
 #pragma unroll
     for (int nu = 0; nu < D; ++nu) {
         if (nu == mu) {
-            if (measure) Alow = A;  // unweighted sum of the planes nu < mu
+            if (measure) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) alow[e * blockDim.x + threadIdx.x] = A.e[e / 3][e % 3];
+            }
             continue;
         }
         const Step fn = step_fwd<D>(rep, x, nu, glued);
@@ -147,29 +153,23 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
         const uint32_t s_mn = x.s + uint32_t(bn.ds), l_mn = layer ^ bn.flip;
         const uint32_t s_pmmn = s_pm + uint32_t(bn.ds), l_pmmn = l_pm ^ bn.flip;
 
-        // forward staple: U_nu(x+mu) streamed by rows
-        {
-            const uint32_t tags = layer + l_pm + l_pn + layer;
-            const mat3<R> u2 = load_link<PREC>(link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn), Vh);
-            const mat3<R> u3 = load_link<PREC>(link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s), Vh);
-            acc_forward_staple<PREC>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), u2, u3, Vh,
-                                     single ? R(1) : R(tags == 0 ? beta0 : beta1));
-        }
-        // backward staple: U_mu(x-nu) and U_nu(x-nu) streamed by rows
-        {
-            const uint32_t tags = l_mn + l_pmmn + layer + l_mn;
-            const mat3<R> u2 = load_link<PREC>(link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), Vh);
-            acc_backward_staple<PREC>(A, link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn), u2,
-                                      link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
-                                      single ? R(1) : R(tags == 0 ? beta0 : beta1));
-        }
+        const uint32_t tags_f = layer + l_pm + l_pn + layer;
+        const uint32_t tags_b = l_mn + l_pmmn + layer + l_mn;
+        acc_plane_staples<PREC>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm),
+                                link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn),
+                                link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
+                                link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn),
+                                link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn),
+                                link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
+                                single ? R(1) : R(tags_f == 0 ? beta0 : beta1),
+                                single ? R(1) : R(tags_b == 0 ? beta0 : beta1));
     }
     if (single) scale(A, R(beta0));
 
     // heatbath in the storage precision (FP64 for the draw, see su2_heatbath)
     const LinkRef uptr = link_ref<D, PREC>(a.links, rep, layer, mu, p, x.s);
     mat3<R> U = load_link<PREC>(uptr, Vh);
-    mat3<R> W = mul_nn(U, A);   // A is not needed past this point (except Alow)
+    mat3<R> W = mul_nn(U, A);   // A is not needed past this point
     const double tr_old = double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 
     const uint32_t lid = ((rep.lat2test ? 0u : layer * rep.V) + x.s) * uint32_t(D) + uint32_t(mu);
@@ -181,7 +181,12 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     // reunitarisation in FP64 in every mode
     mat3<double> Ud = widen<double>(U);
     reunitarize(Ud);
-    if (measure) plaq = re_tr_nn(stored_form<PREC>(Ud), widen<double>(Alow)) * (1.0 / 3.0);
+    if (measure) {
+        mat3<R> Alow;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) Alow.e[e / 3][e % 3] = alow[e * blockDim.x + threadIdx.x];
+        plaq = re_tr_nn(stored_form<PREC>(Ud), widen<double>(Alow)) * (1.0 / 3.0);
+    }
     store_link<PREC>(uptr, Vh, Ud);
 }
 
@@ -331,23 +336,33 @@ __global__ void __launch_bounds__(256, WAVES) update_persistent_kernel(UpdateArg
     }
 }
 
+// Dynamic LDS of an update launch: one staple snapshot per thread when the
+// launch measures plaquettes (parity-1 slices with a measurement buffer).
+template <int PREC>
+static size_t update_lds_bytes(dim3 block, const UpdateArgs &a)
+{
+    using R = typename Store<PREC>::real;
+    return (a.meas != nullptr && a.parity == 1) ? size_t(block.x) * 9 * sizeof(cx<R>) : 0;
+}
+
 template <int D, int PREC>
 static hipError_t launch_update_t(int waves, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
 {
+    const size_t lds = update_lds_bytes<PREC>(block, a);
     if constexpr (D == 4) {
         if (waves == 3) {
-            hipLaunchKernelGGL((update_kernel<D, PREC, 3>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((update_kernel<D, PREC, 3>), grid, block, lds, st, a);
             return hipGetLastError();
         }
         if constexpr (PREC == kFP32_18 || PREC == kFP32_12) {
             if (waves == 4) {
-                hipLaunchKernelGGL((update_kernel<D, PREC, 4>), grid, block, 0, st, a);
+                hipLaunchKernelGGL((update_kernel<D, PREC, 4>), grid, block, lds, st, a);
                 return hipGetLastError();
             }
         }
     }
     if (waves != kDefaultWaves) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves>), grid, block, lds, st, a);
     return hipGetLastError();
 }
 
