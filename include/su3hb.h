@@ -205,9 +205,13 @@ int su3hb_batch_create(su3hb_batch **out, int nd, const su3hb_replica_desc *reps
 
 /* n_sweeps sweeps of every replica at its own beta.  mode 0: one launch per
  * checkerboard slice covering all replicas; mode 1: one persistent
- * cooperative launch per call that loops over sweeps and slices with a grid
- * barrier between slices.  Both give bit-identical links.  stats as in
- * su3hb_sweep, summed over replicas. */
+ * cooperative launch (one 512-thread block per compute unit) that loops over
+ * sweeps and slices with a grid barrier between slices, in launches of at
+ * most 65536 sweeps.  Both give bit-identical links.  Mode 1 returns after
+ * the work has finished (it synchronises the stream); if a grid barrier
+ * waits past its spin limit every block leaves the kernel and the call
+ * returns SU3HB_EHIP with the links not valid.  stats as in su3hb_sweep,
+ * summed over replicas. */
 int su3hb_batch_sweep(su3hb_batch *b, int n_hit, int n_sweeps, int mode, su3hb_stats *stats);
 
 /* Per-replica plaquette: out[6*r .. 6*r+5] as in su3hb_plaquette. */

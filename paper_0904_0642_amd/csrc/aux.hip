@@ -37,7 +37,6 @@ __device__ __forceinline__ void block_sum(double v[NV])
 // the D(D-1)/2 plaquettes based at x,
 // (1/3) Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = (1/3) Re Tr(T1 T2^dag)
 // with T1 = U_mu(x) U_nu(x+mu), T2 = U_nu(x) U_mu(x+nu); products in FP64.
-// All planes of a site are unrolled so their loads are in flight together.
 // Partial sums per block: [spacelike, timelike, layer0, layer1, beta-weighted].
 template <int D, int PREC>
 __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
@@ -45,7 +44,7 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
     const uint32_t lb = blockIdx.x;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (lb < a.total_blocks) {
-        const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, true);
+        const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, kPlaquetteBlocks);
         const RepDesc &rep = a.reps[r];
         const uint32_t glued = rep.nlat == 2 ? rep.glued : 0u;
         const double beta0 = a.use_rep_beta ? rep.beta0 : a.beta0;
@@ -64,13 +63,15 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
             x.from_half(rep, h, p, layer);
             const int q = 1 - p;
             double site_sum = 0.0;
-#pragma unroll
+            // planes one at a time: unrolled, every load of the site would be
+            // hoisted together and the kernel would run at one wave per SIMD
+#pragma unroll 1
             for (int mu = 0; mu < D; ++mu) {
                 const Step fm = step_fwd<D>(rep, x, mu, glued);
                 const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
                 const mat3<double> umx = widen<double>(
                     load_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh));
-#pragma unroll
+#pragma unroll 1
                 for (int nu = mu + 1; nu < D; ++nu) {
                     const Step fn = step_fwd<D>(rep, x, nu, glued);
                     const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
@@ -495,6 +496,12 @@ __global__ void counter_set_kernel(uint32_t *ctr, uint32_t value)
     if (threadIdx.x == 0) atomicExch(ctr, value);
 }
 
+__global__ void u32_zero_kernel(uint32_t *p, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
+}
+
 __global__ void u64_zero_kernel(unsigned long long *p, int n)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -522,6 +529,12 @@ hipError_t launch_counter_add(hipStream_t st, uint32_t *ctr, uint32_t add)
 hipError_t launch_counter_set(hipStream_t st, uint32_t *ctr, uint32_t value)
 {
     hipLaunchKernelGGL(counter_set_kernel, dim3(1), dim3(64), 0, st, ctr, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_u32_zero(hipStream_t st, uint32_t *p, int n)
+{
+    hipLaunchKernelGGL(u32_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

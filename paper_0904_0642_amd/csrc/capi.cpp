@@ -81,8 +81,9 @@ struct su3hb_lattice {
     uint32_t *d_cursor = nullptr;
     unsigned long long *d_maxdef = nullptr;
     double *d_stage = nullptr;
+    uint32_t *d_bar = nullptr;    // grid-barrier counters of persistent launches
     int block = 256, order = 1, waves = kDefaultWaves;
-    uint32_t upd_blocks = 0, plq_blocks = 0;
+    uint32_t upd_blocks = 0, plq_blocks = 0, pers_blocks = 0;
     bool use_graph = true;
     GraphCache graph;
     std::vector<hipEvent_t> events;
@@ -108,7 +109,7 @@ void drop_graph(su3hb_lattice *L)
 void layout_reps(su3hb_lattice *L)
 {
     uint64_t off = 0;
-    uint32_t ub = 0, pb = 0;
+    uint32_t ub = 0, pb = 0, sb = 0;
     const int NE = elems_per_link(L->prec);
     for (auto &r : L->reps) {
         r.elem_offset = off;
@@ -123,9 +124,13 @@ void layout_reps(su3hb_lattice *L)
         r.plq_block0 = pb;
         r.plq_blocks = (nsite + kPlaqBlock * r.plq_spt - 1) / (kPlaqBlock * r.plq_spt);
         pb += r.plq_blocks;
+        r.pers_block0 = sb;
+        r.pers_blocks = (r.nlat * r.Vh + kPersistentThreads - 1) / kPersistentThreads;
+        sb += r.pers_blocks;
     }
     L->upd_blocks = ub;
     L->plq_blocks = pb;
+    L->pers_blocks = sb;
 }
 
 int upload_reps(su3hb_lattice *L)
@@ -189,6 +194,7 @@ int alloc_common(su3hb_lattice *L)
     HIPCHK(hipMalloc(&L->d_series, sizeof(double) * 6 * kSeriesCap));
     HIPCHK(hipMalloc(&L->d_cursor, sizeof(uint32_t)));
     HIPCHK(hipMalloc(&L->d_maxdef, sizeof(unsigned long long)));
+    HIPCHK(hipMalloc(&L->d_bar, sizeof(uint32_t) * kBarrierWords));
     layout_reps(L);
     HIPCHK(hipMalloc(&L->d_partials, sizeof(double) * 5 * L->plq_blocks));
     int rc = upload_reps(L);
@@ -241,6 +247,7 @@ void destroy(su3hb_lattice *L)
     hipFree(L->d_cursor);
     hipFree(L->d_maxdef);
     hipFree(L->d_stage);
+    hipFree(L->d_bar);
     if (L->cap) hipStreamDestroy(L->cap);
     delete L;
 }
@@ -987,15 +994,31 @@ int su3hb_batch_sweep(su3hb_batch *L, int n_hit, int n_sweeps, int mode, su3hb_s
         rc = run_sweeps(L, 0.0, 0.0, n_hit, n_sweeps, 0);
         if (rc) return rc;
     } else if (n_sweeps > 0) {
+        // one resident block per CU (as many as fit), slices separated by a
+        // grid barrier; a barrier that gives up raises a flag checked below
         int per_cu = 0;
-        HIPCHK(persistent_max_blocks(L->nd, L->prec, L->waves, L->block, &per_cu));
+        HIPCHK(persistent_max_blocks(L->nd, L->prec, &per_cu));
         if (per_cu < 1) return fail(SU3HB_EUNSUPPORTED, "persistent kernel cannot be resident");
-        const int blocks = int(std::min<uint64_t>(uint64_t(per_cu) * L->num_cus, L->upd_blocks));
+        const int blocks = int(std::min<uint64_t>(uint64_t(per_cu) * L->num_cus, L->pers_blocks));
         UpdateArgs a = update_args(L, 0.0, 0.0, n_hit);
         a.order = 0;
-        HIPCHK(launch_update_persistent(L->nd, L->prec, L->waves, blocks, L->block, L->stream, a, n_sweeps));
-        HIPCHK(launch_counter_add(L->stream, L->d_sweep, uint32_t(n_sweeps)));
+        a.persistent = 1;
+        a.barrier = L->d_bar;
+        a.total_blocks = L->pers_blocks;
+        // bounded sweeps per launch keep the barrier counters far from overflow
+        constexpr int kChunk = 1 << 16;
+        for (int done = 0; done < n_sweeps;) {
+            const int n = std::min(kChunk, n_sweeps - done);
+            HIPCHK(launch_u32_zero(L->stream, L->d_bar, kBarrierWords));
+            HIPCHK(launch_update_persistent(L->nd, L->prec, blocks, L->stream, a, n));
+            HIPCHK(launch_counter_add(L->stream, L->d_sweep, uint32_t(n)));
+            done += n;
+        }
         L->sweep += uint64_t(n_sweeps);
+        uint32_t flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, L->d_bar + kBarrierFlag, sizeof flag, hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+        if (flag) return fail(SU3HB_EHIP, "persistent sweep: a grid barrier timed out; the links are not valid");
     }
     if (stats) return read_stats(L, stats);
     return SU3HB_OK;

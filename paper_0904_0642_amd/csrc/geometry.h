@@ -7,15 +7,23 @@
 
 namespace su3hb {
 
+// Block partitions of the replicas: per-slice update launches, plaquette
+// launches, persistent launches.
+enum BlockKind { kUpdateBlocks = 0, kPlaquetteBlocks = 1, kPersistentBlocks = 2 };
+
+__device__ __forceinline__ uint32_t first_block(const RepDesc &r, int kind)
+{
+    return kind == kPlaquetteBlocks ? r.plq_block0 : kind == kPersistentBlocks ? r.pers_block0 : r.upd_block0;
+}
+
 // Find the replica owning logical block lb: largest r with first[r] <= lb.
 // The block index and the table are uniform, so this runs on scalar units.
-__device__ __forceinline__ int find_replica(const RepDesc *__restrict__ reps, int nrep, uint32_t lb,
-                                            bool plaquette)
+__device__ __forceinline__ int find_replica(const RepDesc *__restrict__ reps, int nrep, uint32_t lb, int kind)
 {
     int lo = 0, hi = nrep - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const uint32_t first = plaquette ? reps[mid].plq_block0 : reps[mid].upd_block0;
+        const uint32_t first = first_block(reps[mid], kind);
         if (first <= lb) lo = mid; else hi = mid - 1;
     }
     return lo;

@@ -13,9 +13,9 @@ hipError_t launch_update(int D, int prec, int waves, dim3 grid, dim3 block, hipS
                          const UpdateArgs &a);
 
 // persistent cooperative batch sweep: n_sweeps x 2D slices with a grid barrier
-hipError_t launch_update_persistent(int D, int prec, int waves, int blocks, int threads, hipStream_t st,
-                                    const UpdateArgs &a, int n_sweeps);
-hipError_t persistent_max_blocks(int D, int prec, int waves, int threads, int *blocks_per_cu);
+// persistent batch sweeps: kPersistentThreads per block, a.barrier zeroed beforehand
+hipError_t launch_update_persistent(int D, int prec, int blocks, hipStream_t st, const UpdateArgs &a, int n_sweeps);
+hipError_t persistent_max_blocks(int D, int prec, int *blocks_per_cu);
 
 // plaquettes: per-block partial sums, then one block per replica finalises
 hipError_t launch_plaquette(int D, int prec, dim3 grid, dim3 block, hipStream_t st, const PlaqArgs &a);
@@ -47,6 +47,7 @@ hipError_t launch_stats_zero(hipStream_t st, StatSlot *slots);
 hipError_t launch_stats_reduce(hipStream_t st, const StatSlot *slots, StatSlot *out);
 hipError_t launch_counter_add(hipStream_t st, uint32_t *ctr, uint32_t add);
 hipError_t launch_counter_set(hipStream_t st, uint32_t *ctr, uint32_t value);
+hipError_t launch_u32_zero(hipStream_t st, uint32_t *p, int n);
 hipError_t launch_u64_zero(hipStream_t st, unsigned long long *p, int n);
 
 }  // namespace su3hb

@@ -39,7 +39,21 @@ struct RepDesc {
     uint32_t plq_block0;     // first block in a plaquette launch
     uint32_t plq_blocks;
     uint32_t plq_spt;        // plaquettes per thread in the plaquette launch
+    uint32_t pers_block0;    // first block in a persistent launch (kPersistentThreads links per block)
+    uint32_t pers_blocks;
 };
+
+// Persistent batch launches: one block of kPersistentThreads (2 waves per
+// SIMD) per CU, slices separated by a grid barrier on a small array of
+// counters (kBarrierWords words: kBarrierLeaves leaf counters on their own
+// 128-byte lines, the top counter, an abort flag).  Three waves per SIMD
+// would make the FP32 kernels spill and measured slower.
+constexpr int kPersistentThreads = 512;
+constexpr int kBarrierWords = 2048;
+constexpr uint32_t kBarrierLeaves = 16;
+constexpr uint32_t kBarrierTop = 1024;
+constexpr uint32_t kBarrierFlag = 1536;
+constexpr uint32_t kBarrierSpinLimit = 1u << 22;
 
 // Statistics slot, padded to its own 128-byte line.
 struct alignas(128) StatSlot {
@@ -68,6 +82,8 @@ struct UpdateArgs {
     StatSlot *stats;             // kStatSlots slots
     uint32_t total_blocks;       // real blocks (grid may be padded to 8)
     double *meas;                // fused plaquettes: [mu][total_blocks] partial sums, or null
+    int persistent;              // 1: logical blocks of the persistent partition
+    uint32_t *barrier;           // persistent launches: kBarrierWords counters, zeroed before the launch
 };
 
 struct PlaqArgs {

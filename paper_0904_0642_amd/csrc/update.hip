@@ -9,7 +9,6 @@
 // accumulating the change of sum_p beta_p Re Tr U_p / 3 and the counters.
 // The links of one slice are independent (Sec. 2), so one thread owns one
 // link and the slice is one launch.
-#include <hip/hip_cooperative_groups.h>
 
 #include "geometry.h"
 #include "kernels.h"
@@ -204,8 +203,8 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
         dtrace += __shfl_xor(dtrace, off);
         plaq += __shfl_xor(plaq, off);
     }
-    __shared__ int s_int[4][7];
-    __shared__ double s_dbl[4][2];
+    __shared__ int s_int[kPersistentThreads / 64][7];
+    __shared__ double s_dbl[kPersistentThreads / 64][2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
@@ -236,24 +235,34 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
     __syncthreads();  // the shared arrays are reused by the next block in a persistent loop
 }
 
-// Update the links of logical block lb (replica found by binary search);
-// lt_override >= 0 gives the thread's link directly (order 3).
+// Update the links of logical block lb (replica found by binary search),
+// adding to the thread's counters; lt_override >= 0 gives the thread's link
+// directly (order 3).
+template <int D, int PREC>
+__device__ __forceinline__ void block_links(const UpdateArgs &a, uint32_t lb, uint32_t sweep, int att[3], int acc[3],
+                                            int &upd, double &dtrace, double &plaq, int64_t lt_override = -1)
+{
+    if (lb < a.total_blocks) {
+        const int kind = a.persistent ? kPersistentBlocks : kUpdateBlocks;
+        const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, kind);
+        const RepDesc &rep = a.reps[r];
+        const uint32_t lt = lt_override >= 0 ? uint32_t(lt_override)
+                                             : (lb - first_block(rep, kind)) * blockDim.x + threadIdx.x;
+        if (lt < rep.nlat * rep.Vh) {
+            update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
+            ++upd;
+        }
+    }
+}
+
+// One logical block of a per-slice launch, its counters flushed at the end.
 template <int D, int PREC>
 __device__ __forceinline__ void process_block(const UpdateArgs &a, uint32_t lb, uint32_t sweep,
                                               int64_t lt_override = -1)
 {
     int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
     double dtrace = 0.0, plaq = 0.0;
-    if (lb < a.total_blocks) {
-        const int r = a.nrep == 1 ? 0 : find_replica(a.reps, a.nrep, lb, false);
-        const RepDesc &rep = a.reps[r];
-        const uint32_t lt = lt_override >= 0 ? uint32_t(lt_override)
-                                             : (lb - rep.upd_block0) * blockDim.x + threadIdx.x;
-        if (lt < rep.nlat * rep.Vh) {
-            update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
-            upd = 1;
-        }
-    }
+    block_links<D, PREC>(a, lb, sweep, att, acc, upd, dtrace, plaq, lt_override);
     flush_stats(a, lb, att, acc, upd, dtrace, plaq);
 }
 
@@ -312,25 +321,79 @@ __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
         process_block<D, PREC>(a, logical_block(a, blockIdx.x), *a.sweep);
 }
 
-// Persistent form for batches: the grid stays resident for n_sweeps sweeps,
-// loops over the logical blocks of every slice and meets at a grid barrier
-// between slices (the next slice reads links this one wrote).  The sweep
-// number is the counter's value at entry plus the local sweep index; the
-// counter itself is advanced once, by the host, after the launch.
-template <int D, int PREC, int WAVES>
-__global__ void __launch_bounds__(256, WAVES) update_persistent_kernel(UpdateArgs a, int n_sweeps)
+// Grid barrier of a persistent launch (all blocks resident: cooperative
+// launch).  Each block's first thread arrives on one of the leaf counters
+// with release semantics; the last arrival of a leaf adds to the top
+// counter; everybody waits for the top counter to reach its target for
+// generation gen and then acquires.  Counters only grow within a launch, so
+// no reset is needed between generations.  A wait that exceeds the spin
+// limit, or sees the abort flag, raises the flag and returns false so that
+// every block leaves the kernel.
+__device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t gen)
 {
-    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t G = gridDim.x, L = G < kBarrierLeaves ? G : kBarrierLeaves, leaf = blockIdx.x % L;
+        const uint32_t members = (G - leaf + L - 1) / L;
+        const uint32_t old =
+            __hip_atomic_fetch_add(bar + leaf * 32u, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == (gen + 1u) * members)
+            __hip_atomic_fetch_add(bar + kBarrierTop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (gen + 1u) * L;
+        int ok = 1;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(bar + kBarrierTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(bar + kBarrierFlag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                ++spins > kBarrierSpinLimit) {
+                atomicOr(bar + kBarrierFlag, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Persistent form for batches: one block per CU stays resident for n_sweeps
+// sweeps, loops over the logical blocks of every slice and meets the others
+// at a grid barrier between slices (the next slice reads links this one
+// wrote).  Blocks are dealt round-robin to the 8 XCDs, so the blocks of XCD k
+// walk the k-th eighth of the logical blocks together, keeping neighbouring
+// links on one L2.  The sweep number is the counter's value at entry plus
+// the local sweep index; the counter itself is advanced once, by the host,
+// after the launch.
+template <int D, int PREC, int THREADS>
+__global__ void __launch_bounds__(THREADS, THREADS / 256) update_persistent_kernel(UpdateArgs a, int n_sweeps)
+{
     const uint32_t sweep0 = *a.sweep;
+    const uint32_t G = gridDim.x, T = a.total_blocks;
+    uint32_t first = blockIdx.x, last = T, step = G;
+    if (G % 8 == 0 && G >= 8) {
+        const uint32_t chunk = (T + 7) / 8, k = blockIdx.x & 7u;
+        first = k * chunk + (blockIdx.x >> 3);
+        last = min(T, (k + 1) * chunk);
+        step = G / 8;
+    }
+    uint32_t gen = 0;
     for (int sw = 0; sw < n_sweeps; ++sw) {
         for (int p = 0; p < 2; ++p) {
             for (int mu = 0; mu < D; ++mu) {
                 UpdateArgs b = a;
                 b.parity = p;
                 b.mu = mu;
-                for (uint32_t lb = blockIdx.x; lb < a.total_blocks; lb += gridDim.x)
-                    process_block<D, PREC>(b, lb, sweep0 + uint32_t(sw));
-                grid.sync();
+                // the waves of the block run freely over the slice; counters
+                // are flushed once per slice, next to the barrier's own sync
+                int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
+                double dtrace = 0.0, plaq = 0.0;
+                for (uint32_t lb = first; lb < last; lb += step)
+                    block_links<D, PREC>(b, lb, sweep0 + uint32_t(sw), att, acc, upd, dtrace, plaq);
+                flush_stats(b, blockIdx.x, att, acc, upd, dtrace, plaq);
+                if (!grid_barrier(a.barrier, gen++)) return;
             }
         }
     }
@@ -379,28 +442,17 @@ static hipError_t launch_update_d(int prec, int waves, dim3 grid, dim3 block, hi
     }
 }
 
-template <int D, int PREC>
-static const void *persistent_fn(int waves)
+static const void *persistent_fn(int D, int prec)
 {
-    if constexpr (D == 4) {
-        if (waves == 3) return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC, 3>);
-        if constexpr (PREC == kFP32_18 || PREC == kFP32_12)
-            if (waves == 4) return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC, 4>);
-    }
-    if (waves != kDefaultWaves) return nullptr;
-    return reinterpret_cast<const void *>(&update_persistent_kernel<D, PREC, kDefaultWaves>);
-}
-
-static const void *persistent_fn(int D, int prec, int waves)
-{
-#define SU3HB_P(DD)                                                   \
-    case DD:                                                          \
-        switch (prec) {                                               \
-        case kFP64_18: return persistent_fn<DD, kFP64_18>(waves);     \
-        case kFP32_18: return persistent_fn<DD, kFP32_18>(waves);     \
-        case kFP32_12: return persistent_fn<DD, kFP32_12>(waves);     \
-        case kFP64_12: return persistent_fn<DD, kFP64_12>(waves);     \
-        default: return nullptr;                                      \
+#define SU3HB_K(DD, PP) reinterpret_cast<const void *>(&update_persistent_kernel<DD, PP, kPersistentThreads>)
+#define SU3HB_P(DD)                                        \
+    case DD:                                               \
+        switch (prec) {                                    \
+        case kFP64_18: return SU3HB_K(DD, kFP64_18);       \
+        case kFP32_18: return SU3HB_K(DD, kFP32_18);       \
+        case kFP32_12: return SU3HB_K(DD, kFP32_12);       \
+        case kFP64_12: return SU3HB_K(DD, kFP64_12);       \
+        default: return nullptr;                           \
         }
     switch (D) {
         SU3HB_P(2)
@@ -411,24 +463,24 @@ static const void *persistent_fn(int D, int prec, int waves)
     default: return nullptr;
     }
 #undef SU3HB_P
+#undef SU3HB_K
 }
 
-hipError_t persistent_max_blocks(int D, int prec, int waves, int threads, int *blocks_per_cu)
+hipError_t persistent_max_blocks(int D, int prec, int *blocks_per_cu)
 {
-    const void *fn = persistent_fn(D, prec, waves);
+    const void *fn = persistent_fn(D, prec);
     if (!fn) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kPersistentThreads, 0);
 }
 
-hipError_t launch_update_persistent(int D, int prec, int waves, int blocks, int threads, hipStream_t st,
-                                    const UpdateArgs &a, int n_sweeps)
+hipError_t launch_update_persistent(int D, int prec, int blocks, hipStream_t st, const UpdateArgs &a, int n_sweeps)
 {
-    const void *fn = persistent_fn(D, prec, waves);
-    if (!fn) return hipErrorInvalidValue;
+    const void *fn = persistent_fn(D, prec);
+    if (!fn || a.barrier == nullptr || !a.persistent) return hipErrorInvalidValue;
     UpdateArgs args = a;
     int ns = n_sweeps;
     void *params[] = {&args, &ns};
-    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), params, 0, st);
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kPersistentThreads), params, 0, st);
 }
 
 hipError_t launch_update(int D, int prec, int waves, dim3 grid, dim3 block, hipStream_t st,

@@ -300,6 +300,25 @@ def test_batch_replica_equals_single(prec):
         assert np.allclose(pb[r], s.plaquette(beta), rtol=1e-14, atol=0, equal_nan=True)
 
 
+def test_persistent_batch_larger_than_grid():
+    # 40 replicas of 12^4: 840 persistent blocks of 512 links, more than one
+    # per resident block, so every block loops over several logical blocks
+    # between grid barriers; two persistent calls equal one per-slice call
+    # of twice the sweeps, bit for bit, with the same counters
+    reps = [((12, 12, 12, 12), 5.5 + 0.025 * r, 1000 + r, su3hb.HOT) for r in range(40)]
+    b0 = su3hb.Batch(4, reps, precision=su3hb.FP32_18)
+    b1 = su3hb.Batch(4, reps, precision=su3hb.FP32_18)
+    s0 = b0.sweep(n_hit=8, n_sweeps=4, mode=0, stats=True)
+    s1a = b1.sweep(n_hit=8, n_sweeps=2, mode=1, stats=True)
+    s1b = b1.sweep(n_hit=8, n_sweeps=2, mode=1, stats=True)
+    for r in (0, 17, 39):
+        assert np.array_equal(b0.get_links(r), b1.get_links(r)), r
+    for k in ("attempts", "accepts"):
+        assert list(s0[k]) == [a + b for a, b in zip(s1a[k], s1b[k])], k
+    assert s0["link_updates"] == s1a["link_updates"] + s1b["link_updates"] == 4 * 40 * 4 * 12 ** 4
+    assert np.allclose(b0.plaquette(), b1.plaquette(), rtol=0, atol=0, equal_nan=True)
+
+
 @pytest.mark.parametrize("ext,prec,tol", [([8, 8, 8, 8], su3hb.FP64_18, 1e-13), ([6, 4, 8], su3hb.FP64_18, 1e-13),
                                           ([8, 8, 8, 8], su3hb.FP64_12, 1e-13),
                                           ([16, 8], su3hb.FP64_18, 1e-13), ([4, 4, 2, 4, 2], su3hb.FP64_18, 1e-13),
