@@ -104,10 +104,19 @@ __global__ void __launch_bounds__(1024) measure_finalize_kernel(const double *me
                                                                  double *series, uint32_t *cursor)
 {
     double v[2] = {0.0, 0.0};  // spacelike, timelike
+    const uint32_t bd = blockDim.x;
     for (int mu = 1; mu < D; ++mu) {
-        double s = 0.0;
-        for (uint32_t b = threadIdx.x; b < nblocks; b += blockDim.x) s += meas[size_t(mu) * nblocks + b];
-        v[mu == D - 1 ? 1 : 0] += s;
+        // eight independent partial sums (fixed assignment, so the result is
+        // reproducible) keep eight loads in flight per thread
+        const double *m = meas + size_t(mu) * nblocks;
+        double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        uint32_t b = threadIdx.x;
+        for (; b + 7 * bd < nblocks; b += 8 * bd) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += m[b + k * bd];
+        }
+        for (; b < nblocks; b += bd) s[0] += m[b];
+        v[mu == D - 1 ? 1 : 0] += ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
