@@ -37,9 +37,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        # SU3HB_ORACLE_LIB names another build of su3_oracle.c; the mutation
+        # tests use it to run the pins against copies with planted mistakes
+        path = os.environ.get("SU3HB_ORACLE_LIB", "")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = C.CDLL(path)
         u32p = C.POINTER(C.c_uint32)
         dp = C.POINTER(C.c_double)
         L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]

@@ -216,6 +216,38 @@ def test_sweep_argument_errors():
     assert g.get_state()[1] == 0
 
 
+def test_zero_beta_is_degenerate(oracle_mod):
+    # beta = 0: every staple is zero, so every SU(2) projection is degenerate
+    # and every hit is rejected (no proposal is even counted); from the
+    # ordered start the links stay exactly 1, from a random start they only
+    # pass through reunitarisation
+    g, o = pair(oracle_mod, [4, 4, 2, 6], start=su3hb.COLD, seed=4)
+    st = g.sweep(0.0, n_hit=8, n_sweeps=2, stats=True)
+    eye = np.broadcast_to(np.eye(3), g.get_links().shape)
+    assert np.array_equal(g.get_links(), eye)
+    assert list(st["attempts"]) == [0, 0, 0] and list(st["accepts"]) == [0, 0, 0]
+    g, o = pair(oracle_mod, [4, 4, 2, 6], seed=4)
+    st = g.sweep(0.0, n_hit=8, n_sweeps=1, stats=True)
+    st_o = o.sweep(0.0, nhit=8, nsweeps=1)
+    assert list(st["attempts"]) == [0, 0, 0] and list(st_o["attempts"]) == [0, 0, 0]
+    assert maxdiff(g.get_links(), o.get_links()) <= 1e-13
+
+
+@pytest.mark.parametrize("beta,n_hit", [(5.7, 1), (-2.0, 8), (0.3, 200)])
+def test_hit_counts_and_signs(oracle_mod, beta, n_hit):
+    # the paper's default single hit, a negative coupling (the projection
+    # norm absorbs the sign), and a weak coupling with many rejections that
+    # reaches deep into the hit counter
+    g, o = pair(oracle_mod, [6, 4, 4, 4], seed=6)
+    st_g = g.sweep(beta, n_hit=n_hit, n_sweeps=1, stats=True)
+    st_o = o.sweep(beta, nhit=n_hit, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  beta={beta} n_hit={n_hit}: max |dU| = {d:.3e}, attempts {list(st_g['attempts'])}")
+    assert d <= TOL64
+    assert list(st_g["attempts"]) == list(st_o["attempts"])
+    assert list(st_g["accepts"]) == list(st_o["accepts"])
+
+
 def test_resume_is_bitwise(oracle_mod):
     a = su3hb.Lattice([8, 4, 4, 4], seed=21)
     a.sweep(5.8, n_hit=8, n_sweeps=6)

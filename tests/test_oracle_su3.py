@@ -100,3 +100,42 @@ def test_gauge_invariance(oracle_mod, ext, nlat, mask):
                 a = L.staple(layer, s, mu, 5.5, 6.0)
                 ra1.append(np.trace(links1[layer, s, mu] @ a).real)
     assert np.allclose(ra0, ra1, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("ext", [(4, 2, 6, 4), (6, 4, 2), (4, 6)])
+def test_plaquette_split_brute_force(oracle_mod, ext):
+    # brute force on a tiny lattice: the links as an array over the sites
+    # (direction 0 fastest, so the reversed extents in C order), neighbours
+    # by np.roll, every plaquette of every plane, split into planes without
+    # and with direction D-1
+    D = len(ext)
+    L = oracle_mod.Lattice(list(ext), seed=13)
+    L.hot_start()
+    L.sweep(5.0, nhit=2, nsweeps=1)
+    U = L.get_links()[0].reshape(tuple(reversed(ext)) + (D, 3, 3))
+    axis = lambda d: D - 1 - d
+
+    def shift(a, d):  # a(x + d)
+        return np.roll(a, -1, axis=axis(d))
+
+    space = time = 0.0
+    nspace = ntime = 0
+    for mu in range(D):
+        for nu in range(mu + 1, D):
+            umu, unu = U[..., mu, :, :], U[..., nu, :, :]
+            p = umu @ shift(unu, mu) @ np.conj(np.swapaxes(shift(umu, nu), -1, -2)) @ np.conj(np.swapaxes(unu, -1, -2))
+            t = np.trace(p, axis1=-2, axis2=-1).real.sum() / 3.0
+            if nu == D - 1:
+                time += t
+                ntime += p[..., 0, 0].size
+            else:
+                space += t
+                nspace += p[..., 0, 0].size
+    out = L.plaquette(5.0)
+    assert abs(out[0] - (space + time) / (nspace + ntime)) < 1e-13
+    assert abs(out[2] - time / ntime) < 1e-13
+    if nspace:
+        assert abs(out[1] - space / nspace) < 1e-13
+    else:
+        assert np.isnan(out[1])
+    assert abs(out[5] - 5.0 * (space + time)) < 1e-10
