@@ -122,6 +122,44 @@ def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int, la
     return out
 
 
+def overrelax_leg(name: str, steps: int, warmup: int, autotune_ms: int):
+    """Overrelaxation sweeps (per subgroup the reflection that keeps the local
+    action) on a full-size lattice: the same loads and stores as a heatbath
+    sweep without the Kennedy-Pendleton draws, priced with the same bytes."""
+    import torch
+
+    import paper_0904_0642_amd as su3hb
+
+    ext, prec, beta = WORKLOADS[name]
+    D = len(ext)
+    V = int(np.prod(ext))
+    lat = su3hb.Lattice(ext, precision=prec, start=su3hb.HOT, seed=1)
+    if autotune_ms > 0:
+        lat.autotune(autotune_ms)
+    lat.sweep(beta, n_hit=8, n_sweeps=max(warmup, 1))
+    lat.overrelax(beta, n_sweeps=max(warmup, 1))
+    t0 = lat.plaquette(beta)[5]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    timing, _ = lat.sweep_timed(beta, n_hit=0, n_sweeps=steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t
+    upd_ms = timing[0] / max(timing[1], 1)
+    bytes_per_launch = (2 * D + 1) * BYTES_PER_LINK[prec] * (V // 2)
+    achieved = bytes_per_launch / (upd_ms * 1e-3) / 1e9
+    t1 = lat.plaquette(beta)[5]
+    out = {"value": round(steps * V * D / secs, 1), "unit": "link updates/s", "ms_per_step": round(1e3 * secs / steps, 4),
+           "update_kernel_ms": round(upd_ms, 5),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": bytes_per_launch},
+           "action_relative_change": float(abs(t1 - t0) / abs(t0)),
+           "launch": dict(zip(("block", "order", "waves"), lat.get_launch()))}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int = 128):
     """Independent replicas of mixed sizes (8^4, 12^4, 16^3x4 round robin),
     beta uniform in [5.5, 6.5], FP32 links, one launch per slice for all
@@ -340,6 +378,8 @@ def main():
         line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
         line["dlt_2x24^3x8_fp32"] = dlt_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
         line["precision_study"] = precision_study(args.n_hit)
+        line["overrelaxation_" + args.workload] = overrelax_leg(args.workload, args.steps, args.warmup,
+                                                                args.autotune_ms)
         for name in ("64^4-fp32-18", "48^4-fp64-12"):
             if name in (args.workload, args.compare):
                 continue

@@ -124,6 +124,19 @@ void su3hb_free(su3hb_lattice *lat);
 int su3hb_sweep(su3hb_lattice *lat, double beta0, double beta1, int n_hit, int n_sweeps,
                 su3hb_stats *stats);
 
+/* n_sweeps overrelaxation sweeps: the order of su3hb_sweep, each link gets,
+ * per SU(2) subgroup (0,1),(0,2),(1,2), the reflection that keeps its local
+ * action Re Tr(U A) unchanged: with the subgroup block of W = U A equal to
+ * k V, V in SU(2), the block becomes k V^dag (U <- R U, r = V^dag V^dag),
+ * then reunitarisation.  Sec. 1 of the paper names overrelaxation moves as
+ * an addition the code could take in; interleaved with heatbath sweeps they
+ * leave the Boltzmann distribution invariant.  No random numbers are drawn;
+ * the sweep counter advances by n_sweeps.  stats: attempts and accepts both
+ * count the reflections (subgroups with k > 1e-300), dtrace is the change of
+ * the action (zero up to rounding).  Errors and synchronisation as
+ * su3hb_sweep. */
+int su3hb_overrelax(su3hb_lattice *lat, double beta0, double beta1, int n_sweeps, su3hb_stats *stats);
+
 /* As su3hb_sweep, measuring the plaquettes after every sweep (Sec. 2.4,
  * measurement step) into series[6*i .. 6*i+5] for sweep i (the layout of
  * su3hb_plaquette).  Synchronises once at the end. */
@@ -176,7 +189,8 @@ int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *order, int *wave
 int su3hb_autotune(su3hb_lattice *lat, int budget_ms);
 
 /* As su3hb_sweep (measure != 0: plus plaquettes into series as in
- * su3hb_sweep_measure), launched kernel by kernel with a HIP event pair
+ * su3hb_sweep_measure; n_hit = 0: overrelaxation sweeps as in
+ * su3hb_overrelax), launched kernel by kernel with a HIP event pair
  * around every launch on the lattice's stream.  timing[0] = summed update
  * kernel time (ms), timing[1] = number of update launches, timing[2] =
  * summed plaquette kernel time (ms), timing[3] = number of plaquette

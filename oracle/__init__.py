@@ -54,6 +54,7 @@ def lib():
         L.or_kp_draw.argtypes = [C.c_double, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                                  dp, C.POINTER(C.c_uint64)]
         L.or_kp_draw.restype = C.c_int
+        L.or_reflect_matrix.argtypes = [dp, dp]
         L.or_cm_update_matrix.argtypes = [dp, dp, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
                                           C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.or_create.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_int, C.c_uint, C.c_int, C.c_uint64]
@@ -134,6 +135,14 @@ def cm_update_matrix(u: np.ndarray, a: np.ndarray, nhit: int, seed: int, lid: in
     ac = (C.c_uint64 * 3)()
     lib().or_cm_update_matrix(_dptr(uu), _dptr(aa), nhit, seed, lid, sweep, at, ac)
     return uu.view(np.complex128).reshape(3, 3), list(at), list(ac)
+
+
+def reflect_matrix(u: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """One overrelaxation step of matrix u for staple a (three subgroup reflections)."""
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(3, 3)).view(np.float64).copy()
+    aa = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(3, 3)).view(np.float64).copy()
+    lib().or_reflect_matrix(_dptr(uu), _dptr(aa))
+    return uu.view(np.complex128).reshape(3, 3)
 
 
 class Lattice:
@@ -246,6 +255,10 @@ class Lattice:
         lib().or_sweep(self._h, float(beta0), float(beta1), int(nhit), int(nsweeps), _dptr(st))
         return {"attempts": st[0:3].astype(np.int64), "accepts": st[3:6].astype(np.int64),
                 "dtrace": float(st[6])}
+
+    def overrelax(self, beta0, beta1=None, nsweeps=1) -> dict:
+        """Overrelaxation sweeps (a sweep with no heatbath hits)."""
+        return self.sweep(beta0, beta1, nhit=0, nsweeps=nsweeps)
 
     def plaquette(self, beta0=0.0, beta1=None) -> np.ndarray:
         """[total, spacelike, timelike, layer0, layer1, beta-weighted trace sum]."""

@@ -42,6 +42,12 @@
  *   R-RNG    Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
  *            64-bit seed, counter (link id, sweep, (sub<<16)|(hit<<1)|blk,
  *            stream tag); 32-bit words map to uniforms (r+1)/2^32 in (0,1].
+ *   R-OR     overrelaxation, which Sec. 1 names as a move the code could
+ *            take in: per SU(2) subgroup, in the CM order, the reflection
+ *            that keeps Re Tr(U A) fixed.  With the subgroup block of W = U A
+ *            equal to k V (V in SU(2)), the block becomes k V^dag, i.e.
+ *            U <- R(r) U with r = V^dag V^dag; no random numbers; a sweep
+ *            with n_hit = 0 is an overrelaxation sweep.
  */
 #include <complex.h>
 #include <math.h>
@@ -328,6 +334,44 @@ static void cm_update(su3 *u, const su3 *a, int nhit, const uint32_t key[2], uin
     reunitarize(u);
 }
 
+/* Overrelaxation (reading R-OR): per SU(2) subgroup, the block k V of
+ * W = U A becomes k V^dag, which leaves Re Tr(U A) unchanged, by U <- R U with
+ * r = V^dag V^dag; then reunitarisation.  A degenerate projection (k <= 1e-300)
+ * leaves the subgroup alone.  attempts and accepts count the reflections. */
+static void cm_reflect(su3 *u, const su3 *a, uint64_t attempts[3], uint64_t accepts[3])
+{
+    for (int sub = 0; sub < 3; ++sub) {
+        int i = SUB_I[sub], j = SUB_J[sub];
+        su3 w = mat_mul(u, a);
+        double a0 = creal(w.m[i][i] + w.m[j][j]) / 2;
+        double a1 = cimag(w.m[i][j] + w.m[j][i]) / 2;
+        double a2 = creal(w.m[i][j] - w.m[j][i]) / 2;
+        double a3 = cimag(w.m[i][i] - w.m[j][j]) / 2;
+        double k = sqrt(a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3);
+        if (!(k > 1e-300)) continue;
+        ++attempts[sub];
+        ++accepts[sub];
+        cplx Vd[2][2] = {{(a0 - I * a3) / k, (-a2 - I * a1) / k},
+                         {(a2 - I * a1) / k, (a0 + I * a3) / k}};
+        cplx R[2][2];
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) R[p][q] = Vd[p][0] * Vd[0][q] + Vd[p][1] * Vd[1][q];
+        for (int c = 0; c < 3; ++c) {
+            cplx ui = u->m[i][c], uj = u->m[j][c];
+            u->m[i][c] = R[0][0] * ui + R[0][1] * uj;
+            u->m[j][c] = R[1][0] * ui + R[1][1] * uj;
+        }
+    }
+    reunitarize(u);
+}
+
+/* Test hook: one overrelaxation step of the matrix u18 for the staple a18. */
+void or_reflect_matrix(double *u18, const double *a18)
+{
+    uint64_t at[3] = {0, 0, 0}, ac[3] = {0, 0, 0};
+    cm_reflect((su3 *)u18, (const su3 *)a18, at, ac);
+}
+
 /* Test hook: CM-update one matrix u18 for the staple a18. */
 void or_cm_update_matrix(double *u18, const double *a18, int nhit, uint64_t seed, uint32_t lid,
                          uint32_t sweep, uint64_t attempts[3], uint64_t accepts[3])
@@ -475,7 +519,10 @@ static double update_link(olat *L, int layer, long s, int mu, double beta0, doub
     staple(L, layer, s, mu, beta0, beta1, &A);
     su3 *U = link_at(L, layer, s, mu);
     su3 old = *U;
-    cm_update(U, &A, nhit, L->key, link_id(L, layer, s, mu), L->sweep, attempts, accepts);
+    if (nhit == 0)
+        cm_reflect(U, &A, attempts, accepts);   /* overrelaxation, reading R-OR */
+    else
+        cm_update(U, &A, nhit, L->key, link_id(L, layer, s, mu), L->sweep, attempts, accepts);
     su3 d;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) d.m[i][j] = U->m[i][j] - old.m[i][j];
@@ -523,7 +570,9 @@ double or_update_slice(void *h, int p, int mu, double beta0, double beta1, int n
     return update_slice((olat *)h, p, mu, beta0, beta1, nhit, order, at, ac);
 }
 
-/* stats (may be NULL): [attempts x3, accepts x3, dtrace] as doubles. */
+/* stats (may be NULL): [attempts x3, accepts x3, dtrace] as doubles.
+ * nhit = 0 makes every sweep an overrelaxation sweep (reading R-OR); every
+ * sweep, of either kind, advances the sweep counter. */
 void or_sweep(void *h, double beta0, double beta1, int nhit, int nsweeps, double *stats)
 {
     olat *L = (olat *)h;

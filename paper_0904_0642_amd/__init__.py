@@ -57,6 +57,7 @@ _SIGS = {
     "su3hb_init_lattice": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(su3hb_params)]),
     "su3hb_free": (None, [C.c_void_p]),
     "su3hb_sweep": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(su3hb_stats)]),
+    "su3hb_overrelax": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int, C.POINTER(su3hb_stats)]),
     "su3hb_sweep_measure": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int,
                                       C.POINTER(C.c_double), C.POINTER(su3hb_stats)]),
     "su3hb_plaquette": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_double)]),
@@ -156,6 +157,13 @@ def su3hb_sweep(h, beta0, beta1, n_hit, n_sweeps, want_stats=False):
     st = su3hb_stats() if want_stats else None
     _check(lib().su3hb_sweep(h, float(beta0), float(beta1), int(n_hit), int(n_sweeps),
                              C.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def su3hb_overrelax(h, beta0, beta1, n_sweeps, want_stats=False):
+    st = su3hb_stats() if want_stats else None
+    _check(lib().su3hb_overrelax(h, float(beta0), float(beta1), int(n_sweeps),
+                                 C.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 
@@ -307,6 +315,9 @@ class Lattice:
 
     def sweep(self, beta0, beta1=None, n_hit=8, n_sweeps=1, stats=False):
         return su3hb_sweep(self._h, beta0, beta0 if beta1 is None else beta1, n_hit, n_sweeps, stats)
+
+    def overrelax(self, beta0, beta1=None, n_sweeps=1, stats=False):
+        return su3hb_overrelax(self._h, beta0, beta0 if beta1 is None else beta1, n_sweeps, stats)
 
     def sweep_measure(self, beta0, beta1=None, n_hit=8, n_sweeps=1, stats=False):
         return su3hb_sweep_measure(self._h, beta0, beta0 if beta1 is None else beta1, n_hit, n_sweeps, stats)

@@ -47,13 +47,18 @@ constexpr int kPlaqBlock = 256;
 constexpr uint32_t kSeriesCap = 4096;
 constexpr size_t kStageBytes = size_t(256) << 20;
 
+// A captured sweep, keyed by its couplings, kind (n_hit; 0 = overrelaxation)
+// and measurement.  A few are kept so that heatbath and overrelaxation sweeps
+// can alternate without capturing again.
 struct GraphCache {
     bool valid = false;
     double b0 = 0, b1 = 0;
     int nhit = 0, measure = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
 };
+constexpr int kGraphSlots = 4;
 
 }  // namespace
 
@@ -85,7 +90,8 @@ struct su3hb_lattice {
     int block = 256, order = 1, waves = kDefaultWaves;
     uint32_t upd_blocks = 0, plq_blocks = 0, pers_blocks = 0;
     bool use_graph = true;
-    GraphCache graph;
+    GraphCache graphs[kGraphSlots];
+    uint64_t graph_tick = 0;
     std::vector<hipEvent_t> events;
     int num_cus = 0;
 };
@@ -98,11 +104,16 @@ struct Shape {
 };
 std::map<std::string, Shape> g_tune_cache;
 
+void drop_slot(GraphCache &g)
+{
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+    g = GraphCache{};
+}
+
 void drop_graph(su3hb_lattice *L)
 {
-    if (L->graph.exec) hipGraphExecDestroy(L->graph.exec);
-    if (L->graph.graph) hipGraphDestroy(L->graph.graph);
-    L->graph = GraphCache{};
+    for (auto &g : L->graphs) drop_slot(g);
 }
 
 // Block tables and offsets of every replica for the current launch shape.
@@ -431,11 +442,22 @@ int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nh
     return SU3HB_OK;
 }
 
-int get_graph(su3hb_lattice *L, double b0, double b1, int nhit, int measure)
+int get_graph(su3hb_lattice *L, double b0, double b1, int nhit, int measure, hipGraphExec_t *out)
 {
-    GraphCache &g = L->graph;
-    if (g.valid && g.b0 == b0 && g.b1 == b1 && g.nhit == nhit && g.measure == measure) return SU3HB_OK;
-    drop_graph(L);
+    GraphCache *slot = nullptr;
+    for (auto &g : L->graphs)
+        if (g.valid && g.b0 == b0 && g.b1 == b1 && g.nhit == nhit && g.measure == measure) {
+            g.used = ++L->graph_tick;
+            *out = g.exec;
+            return SU3HB_OK;
+        }
+    // an empty slot, else the least recently used one
+    for (auto &g : L->graphs)
+        if (!slot || !g.valid || (slot->valid && g.used < slot->used)) {
+            slot = &g;
+            if (!g.valid) break;
+        }
+    drop_slot(*slot);
     HIPCHK(hipStreamBeginCapture(L->cap, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_sweep(L, L->cap, b0, b1, nhit, measure);
     hipGraph_t graph = nullptr;
@@ -451,13 +473,15 @@ int get_graph(su3hb_lattice *L, double b0, double b1, int nhit, int measure)
         hipGraphDestroy(graph);
         return fail(SU3HB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
-    g.valid = true;
-    g.b0 = b0;
-    g.b1 = b1;
-    g.nhit = nhit;
-    g.measure = measure;
-    g.graph = graph;
-    g.exec = exec;
+    slot->valid = true;
+    slot->b0 = b0;
+    slot->b1 = b1;
+    slot->nhit = nhit;
+    slot->measure = measure;
+    slot->graph = graph;
+    slot->exec = exec;
+    slot->used = ++L->graph_tick;
+    *out = exec;
     return SU3HB_OK;
 }
 
@@ -469,9 +493,10 @@ int run_sweeps(su3hb_lattice *L, double b0, double b1, int nhit, int n, int meas
         if (rc) return rc;
     }
     if (L->use_graph) {
-        int rc = get_graph(L, b0, b1, nhit, measure);
+        hipGraphExec_t exec = nullptr;
+        int rc = get_graph(L, b0, b1, nhit, measure, &exec);
         if (rc) return rc;
-        for (int i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(L->graph.exec, L->stream));
+        for (int i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(exec, L->stream));
     } else {
         for (int i = 0; i < n; ++i) {
             int rc = enqueue_sweep(L, L->stream, b0, b1, nhit, measure);
@@ -698,6 +723,19 @@ int su3hb_sweep(su3hb_lattice *L, double beta0, double beta1, int n_hit, int n_s
     return SU3HB_OK;
 }
 
+int su3hb_overrelax(su3hb_lattice *L, double beta0, double beta1, int n_sweeps, su3hb_stats *stats)
+{
+    if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
+    int rc = check_sweep_args(beta0, beta1, 1, n_sweeps);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(L->device));
+    if (stats) HIPCHK(launch_stats_zero(L->stream, L->d_stats));
+    rc = run_sweeps(L, beta0, beta1, 0, n_sweeps, 0);  // n_hit 0: overrelaxation
+    if (rc) return rc;
+    if (stats) return read_stats(L, stats);
+    return SU3HB_OK;
+}
+
 int su3hb_sweep_measure(su3hb_lattice *L, double beta0, double beta1, int n_hit, int n_sweeps, double *series,
                         su3hb_stats *stats)
 {
@@ -886,7 +924,7 @@ int su3hb_sweep_timed(su3hb_lattice *L, double beta0, double beta1, int n_hit, i
     if (measure && !series && n_sweeps > 0) return fail(SU3HB_EINVAL, "series is NULL");
     if (measure && n_sweeps > int(kSeriesCap))
         return fail(SU3HB_EINVAL, "at most %u measured sweeps per call", kSeriesCap);
-    int rc = check_sweep_args(beta0, beta1, n_hit, n_sweeps);
+    int rc = check_sweep_args(beta0, beta1, n_hit == 0 ? 1 : n_hit, n_sweeps);  // 0: overrelaxation
     if (rc) return rc;
     HIPCHK(hipSetDevice(L->device));
     if (measure && fused_measure(L)) {

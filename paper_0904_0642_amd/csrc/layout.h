@@ -69,7 +69,7 @@ struct UpdateArgs {
     int nrep;
     int parity;                  // checkerboard colour being updated
     int mu;                      // direction being updated
-    int nhit;                    // KP proposals per subgroup, at most
+    int nhit;                    // KP proposals per subgroup, at most; 0: overrelaxation
     int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
     int order;                   // 0 hardware, 1 XCD-contiguous, 2 XCD slabs, 3 XCD slabs of 3D blocks
     uint32_t slab;               // orders 2, 3: tiles of the last direction per XCD

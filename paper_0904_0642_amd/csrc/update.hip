@@ -15,6 +15,29 @@
 
 namespace su3hb {
 
+// U <- R_IJ(r) U and W <- R_IJ(r) W: the 2x2 matrix r mixes rows I and J.
+template <typename H, int I, int J>
+__device__ __forceinline__ void rotate_rows(mat3<H> &U, mat3<H> &W, const cx<H> &r00, const cx<H> &r01,
+                                            const cx<H> &r10, const cx<H> &r11)
+{
+    const H z = H(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<H> ui = U.e[I][c], uj = U.e[J][c];
+        cx<H> ni{z, z}, nj{z, z};
+        cfma(ni, r00, ui); cfma(ni, r01, uj);
+        cfma(nj, r10, ui); cfma(nj, r11, uj);
+        U.e[I][c] = ni;
+        U.e[J][c] = nj;
+        const cx<H> wi = W.e[I][c], wj = W.e[J][c];
+        cx<H> mi{z, z}, mj{z, z};
+        cfma(mi, r00, wi); cfma(mi, r01, wj);
+        cfma(mj, r10, wi); cfma(mj, r11, wj);
+        W.e[I][c] = mi;
+        W.e[J][c] = mj;
+    }
+}
+
 // One SU(2)-subgroup heatbath on rows (I, J) of U (and W = U A), with U, W
 // and the rotation in H (double for FP64 storage, float for FP32 storage).
 // The norm k, alpha and the Kennedy-Pendleton draw and acceptance test are
@@ -77,22 +100,35 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
     cfma(r10, X10, V00); cfma(r10, X11, V10);
     cfma(r11, X10, V01); cfma(r11, X11, V11);
 
-    // U <- R_IJ(r) U and W <- R_IJ(r) W (rows I and J)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const cx<H> ui = U.e[I][c], uj = U.e[J][c];
-        cx<H> ni{z, z}, nj{z, z};
-        cfma(ni, r00, ui); cfma(ni, r01, uj);
-        cfma(nj, r10, ui); cfma(nj, r11, uj);
-        U.e[I][c] = ni;
-        U.e[J][c] = nj;
-        const cx<H> wi = W.e[I][c], wj = W.e[J][c];
-        cx<H> mi{z, z}, mj{z, z};
-        cfma(mi, r00, wi); cfma(mi, r01, wj);
-        cfma(mj, r10, wi); cfma(mj, r11, wj);
-        W.e[I][c] = mi;
-        W.e[J][c] = mj;
-    }
+    rotate_rows<H, I, J>(U, W, r00, r01, r10, r11);
+}
+
+// Overrelaxation on rows (I, J): the reflection that keeps Re Tr(U A).  With
+// the block of W = U A equal to k V (V in SU(2)) the block becomes k V^dag:
+// U <- R_IJ(r) U with r = V^dag V^dag.  The projection is FP64 as in the
+// heatbath; the rotation is in H.  No random numbers.
+template <typename H, int I, int J>
+__device__ __forceinline__ void su2_reflect(mat3<H> &U, mat3<H> &W, int &attempts, int &accepts)
+{
+    const double a0 = 0.5 * (double(W.e[I][I].re) + double(W.e[J][J].re));
+    const double a1 = 0.5 * (double(W.e[I][J].im) + double(W.e[J][I].im));
+    const double a2 = 0.5 * (double(W.e[I][J].re) - double(W.e[J][I].re));
+    const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
+    const double k = sqrt(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))));
+    if (!(k > 1e-300)) return;  // degenerate projection: no reflection
+    ++attempts;
+    ++accepts;
+    const double ik = 1.0 / k;
+    const double b0 = a0 * ik, b1 = a1 * ik, b2 = a2 * ik, b3 = a3 * ik;
+    // V^dag = [[b0 - i b3, -b2 - i b1], [b2 - i b1, b0 + i b3]], r = V^dag V^dag
+    const cx<double> V00{b0, -b3}, V01{-b2, -b1}, V10{b2, -b1}, V11{b0, b3};
+    cx<double> q00{0.0, 0.0}, q01{0.0, 0.0}, q10{0.0, 0.0}, q11{0.0, 0.0};
+    cfma(q00, V00, V00); cfma(q00, V01, V10);
+    cfma(q01, V00, V01); cfma(q01, V01, V11);
+    cfma(q10, V10, V00); cfma(q10, V11, V10);
+    cfma(q11, V10, V01); cfma(q11, V11, V11);
+    rotate_rows<H, I, J>(U, W, cx<H>{H(q00.re), H(q00.im)}, cx<H>{H(q01.re), H(q01.im)},
+                         cx<H>{H(q10.re), H(q10.im)}, cx<H>{H(q11.re), H(q11.im)});
 }
 
 // Update one link.  On a single-layer lattice every plaquette carries beta0,
@@ -172,9 +208,15 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     const double tr_old = double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 
     const uint32_t lid = ((rep.lat2test ? 0u : layer * rep.V) + x.s) * uint32_t(D) + uint32_t(mu);
-    su2_heatbath<R, 0, 1, 0>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[0], acc[0]);
-    su2_heatbath<R, 0, 2, 1>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[1], acc[1]);
-    su2_heatbath<R, 1, 2, 2>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[2], acc[2]);
+    if (a.nhit > 0) {
+        su2_heatbath<R, 0, 1, 0>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[0], acc[0]);
+        su2_heatbath<R, 0, 2, 1>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[1], acc[1]);
+        su2_heatbath<R, 1, 2, 2>(U, W, lid, sweep, a.nhit, rep.key0, rep.key1, att[2], acc[2]);
+    } else {  // n_hit 0: overrelaxation sweep
+        su2_reflect<R, 0, 1>(U, W, att[0], acc[0]);
+        su2_reflect<R, 0, 2>(U, W, att[1], acc[1]);
+        su2_reflect<R, 1, 2>(U, W, att[2], acc[2]);
+    }
     // W was rotated with U, so Re Tr W is now Re Tr(U' A)
     dtrace += (double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re) - tr_old) * (1.0 / 3.0);
     // reunitarisation in FP64 in every mode

@@ -248,6 +248,51 @@ def test_hit_counts_and_signs(oracle_mod, beta, n_hit):
     assert list(st_g["accepts"]) == list(st_o["accepts"])
 
 
+@pytest.mark.parametrize("ext,nlat,mask,b0,b1,prec,tol", [
+    ([8, 4, 4, 6], 1, 0, 6.0, 6.0, su3hb.FP64_18, TOL64),
+    ([4, 6, 4, 2], 2, 0b1111, 5.5, 6.2, su3hb.FP64_18, TOL64),
+    ([6, 4, 8], 1, 0, 5.0, 5.0, su3hb.FP64_12, TOL64),
+    ([8, 4, 4, 6], 1, 0, 6.0, 6.0, su3hb.FP32_12, TOL32)])
+def test_overrelaxation_matches_oracle(oracle_mod, ext, nlat, mask, b0, b1, prec, tol):
+    # one heatbath sweep, then overrelaxation sweeps (no random numbers):
+    # two in FP64 storage, one in FP32 storage (the FP32 bar is one update
+    # per link from a shared start); counters are the reflections, the action
+    # change is rounding only
+    n_or = 2 if prec in (su3hb.FP64_18, su3hb.FP64_12) else 1
+    g, o = pair(oracle_mod, ext, nlat=nlat, mask=mask, prec=prec, seed=12)
+    if prec != su3hb.FP64_18:
+        o.set_links(g.get_links())
+    g.sweep(b0, b1, n_hit=8, n_sweeps=1)
+    o.sweep(b0, b1, nhit=8, nsweeps=1)
+    if prec in (su3hb.FP32_18, su3hb.FP32_12):
+        o.set_links(g.get_links())
+    t0 = g.plaquette(b0, b1)[5]
+    st_g = g.overrelax(b0, b1, n_sweeps=n_or, stats=True)
+    st_o = o.overrelax(b0, b1, nsweeps=n_or)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  OR ext={ext} nlat={nlat} prec={prec}: max |dU| = {d:.3e}, dtrace {st_g['dtrace']:.2e}")
+    assert d <= tol
+    assert list(st_g["attempts"]) == list(st_o["attempts"]) == [n_or * nlat * int(np.prod(ext)) * len(ext)] * 3
+    rel = 1e-11 if prec in (su3hb.FP64_18, su3hb.FP64_12) else 1e-5
+    assert abs(st_g["dtrace"]) <= rel * abs(t0)
+    assert abs(g.plaquette(b0, b1)[5] - t0) <= rel * abs(t0)
+    assert g.get_state()[1] == o.sweep_counter == 1 + n_or
+
+
+def test_overrelaxation_graphs_equal_direct_launches():
+    # heatbath and overrelaxation calls alternating through the graph cache
+    # give the same links as the same sweeps launched kernel by kernel
+    a = su3hb.Lattice([8, 8, 4, 4], seed=31)
+    b = su3hb.Lattice([8, 8, 4, 4], seed=31)
+    for _ in range(3):
+        a.sweep(5.9, n_hit=8, n_sweeps=1)
+        a.overrelax(5.9, n_sweeps=2)
+        b.sweep_timed(5.9, n_hit=8, n_sweeps=1)
+        b.sweep_timed(5.9, n_hit=0, n_sweeps=2)
+    assert np.array_equal(a.get_links(), b.get_links(), equal_nan=True)
+    assert a.get_state() == b.get_state()
+
+
 def test_resume_is_bitwise(oracle_mod):
     a = su3hb.Lattice([8, 4, 4, 4], seed=21)
     a.sweep(5.8, n_hit=8, n_sweeps=6)

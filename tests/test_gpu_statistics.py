@@ -49,6 +49,23 @@ def test_2d_32x32_exact():
     assert gaussian_difference_q(m, e, u_exact(4.0), 0.0) > QMIN
 
 
+def test_2d_heatbath_with_overrelaxation_exact():
+    # one heatbath sweep and two overrelaxation sweeps per measurement leave
+    # the Boltzmann distribution in place: <P> = u(4) on 32^2
+    lat = su3hb.Lattice([32, 32], seed=11)
+    for _ in range(200):
+        lat.sweep(4.0, n_hit=8, n_sweeps=1)
+        lat.overrelax(4.0, n_sweeps=2)
+    s = []
+    for _ in range(8000):
+        lat.sweep(4.0, n_hit=8, n_sweeps=1)
+        lat.overrelax(4.0, n_sweeps=2)
+        s.append(lat.plaquette(4.0)[0])
+    m, e = jackknife_mean(np.array(s), 32)
+    say(f"  2D 32^2 beta=4 HB+2OR: <P> = {m:.6f} +- {e:.6f}, exact {u_exact(4.0):.6f}")
+    assert gaussian_difference_q(m, e, u_exact(4.0), 0.0) > QMIN
+
+
 @pytest.mark.parametrize("mask", [0b11, 0b01])
 def test_2d_double_layered_exact(mask):
     lat = su3hb.Lattice([16, 16], nlat=2, dlt_mask=mask, seed=2)

@@ -44,12 +44,14 @@ MUTANTS = {
     "forward staple ignores the tag rule": ("double bf = tags == 0 ? beta0 : beta1;", "double bf = beta0;"),
     "timelike planes mislabelled": ("if (nu == D - 1) time += P; else space += P;",
                                     "if (mu == 0) time += P; else space += P;"),
+    "overrelaxation r = V^dag instead of V^dag V^dag": ("R[p][q] = Vd[p][0] * Vd[0][q] + Vd[p][1] * Vd[1][q];",
+                                                         "R[p][q] = Vd[p][q];"),
     "lat2test keeps the layer in the link id": ("long base = L->lat2test ? 0 : (long)layer * L->V;",
                                                 "long base = (long)layer * L->V;"),
 }
 
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_geometry.py", "tests/test_oracle_su3.py",
-        "tests/test_oracle_heatbath.py", "tests/test_oracle_physics.py"]
+        "tests/test_oracle_heatbath.py", "tests/test_oracle_overrelax.py", "tests/test_oracle_physics.py"]
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +62,9 @@ def source():
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(source, name):
     old, new = MUTANTS[name]
-    assert source.count(old) == 1, f"mutation site for '{name}' not unique in the oracle"
+    # the mistake goes in wherever the line occurs (the heatbath and the
+    # overrelaxation share the subgroup projection)
+    assert source.count(old) >= 1, f"mutation site for '{name}' not found in the oracle"
     with tempfile.TemporaryDirectory() as tmp:
         src = os.path.join(tmp, "su3_oracle.c")
         lib = os.path.join(tmp, "liboracle.so")
