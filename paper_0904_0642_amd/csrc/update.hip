@@ -53,7 +53,9 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
     const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
     const double k = sqrt(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))));
     if (!(k > 1e-300)) return;  // degenerate projection: every hit rejected
-    const double alpha = 2.0 * k / 3.0;
+    // alpha = 2k/3; the draw multiplies by 1/alpha = 1.5/k, computed once
+    const double ik = 1.0 / k;
+    const double inv_alpha = 1.5 * ik;
 
     // multi-hit Kennedy-Pendleton: delta = 1 - x0 ~ sqrt(delta) exp(-alpha delta),
     // accepted with probability sqrt(1 - delta/2)
@@ -65,7 +67,7 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
             make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1), kTagUpdate), k0, k1);
         ++attempts;
         const double c = cospi(2.0 * u01(r.y));  // cos(2 pi u)
-        delta = -(log(u01(r.x)) + c * c * log(u01(r.z))) / alpha;
+        delta = -(log(u01(r.x)) + c * c * log(u01(r.z))) * inv_alpha;
         const double r4 = u01(r.w);
         if (r4 * r4 <= 1.0 - 0.5 * delta) {
             ok = true;
@@ -89,7 +91,6 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
 
     // r = X V^dag, X = [[x0 + i x3, x2 + i x1], [-x2 + i x1, x0 - i x3]],
     // V^dag = [[a0 - i a3, -a2 - i a1], [a2 - i a1, a0 + i a3]] / k
-    const double ik = 1.0 / k;
     const H b0 = H(a0 * ik), b1 = H(a1 * ik), b2 = H(a2 * ik), b3 = H(a3 * ik);
     const cx<H> X00{x0, x3}, X01{x2, x1}, X10{-x2, x1}, X11{x0, -x3};
     const cx<H> V00{b0, -b3}, V01{-b2, -b1}, V10{b2, -b1}, V11{b0, b3};
