@@ -61,3 +61,19 @@ def x0_cdf(alpha: float):
     cdf = integrate.cumulative_trapezoid(pdf, xs, initial=0.0)
     cdf /= cdf[-1]
     return lambda x: np.interp(x, xs, cdf)
+
+
+def dlt_two_coupling_exact(n0, n1, beta0, beta1):
+    """Exact 2D double-layered torus, both directions glued, two couplings.
+    On a closed 2D surface every plaquette is an independent variable up to
+    exponentially small global constraints, so <P_p> = u(beta_p).  A layer-0
+    plaquette keeps all four links in layer 0 (tag rule: beta0) unless it
+    touches the last row or column, whose forward neighbours sit in layer 1;
+    every other plaquette carries beta1.  Returns the layer-0 and layer-1
+    averages and the weighted sum sum_p beta_p <P_p>."""
+    n = n0 * n1
+    n_b0 = (n0 - 1) * (n1 - 1)
+    u0, u1 = u_exact(beta0), u_exact(beta1)
+    layer0 = (n_b0 * u0 + (n - n_b0) * u1) / n
+    weighted = n_b0 * beta0 * u0 + (2 * n - n_b0) * beta1 * u1
+    return layer0, u1, weighted

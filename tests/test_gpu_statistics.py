@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 import paper_0904_0642_amd as su3hb
-from exact_su3 import u_exact
-from stats import gaussian_difference_q, jackknife_mean
+from exact_su3 import dlt_two_coupling_exact, u_exact
+from stats import gaussian_difference_q, jackknife_mean, tau_int
 
 pytestmark = pytest.mark.gpu
 
@@ -75,6 +75,21 @@ def test_2d_double_layered_exact(mask):
     assert gaussian_difference_q(m, e, u_exact(4.0), 0.0) > QMIN
 
 
+def test_2d_double_layered_two_couplings_exact():
+    # beta0 != beta1: per-layer averages and the beta-weighted sum against
+    # the exact 2D values (each plaquette at its own coupling, tag rule)
+    b0, b1 = 4.0, 2.0
+    lat = su3hb.Lattice([16, 16], nlat=2, dlt_mask=0b11, seed=12)
+    lat.sweep(b0, b1, n_hit=8, n_sweeps=200)
+    rows = lat.sweep_measure(b0, b1, n_hit=8, n_sweeps=4000)[:, [3, 4, 5]]
+    exact = dlt_two_coupling_exact(16, 16, b0, b1)
+    for k, name in enumerate(("layer 0", "layer 1", "weighted sum")):
+        m, e = jackknife_mean(rows[:, k], 32)
+        q = gaussian_difference_q(m, e, exact[k], 0.0)
+        say(f"  2D DLT beta=({b0},{b1}) {name}: {m:.6f} +- {e:.6f}, exact {exact[k]:.6f}, Q={q:.2f}")
+        assert q > QMIN
+
+
 def test_4d_strong_coupling():
     lat = su3hb.Lattice([8, 8, 8, 8], seed=3)
     s = run_series(lat, 1.0, ntherm=100, nmeas=3000)
@@ -95,13 +110,28 @@ def test_paper_4x4x4x4_beta5p6_ordered():
     q1 = gaussian_difference_q(m, e, *ref["act_single"])
     q2 = gaussian_difference_q(m, e, *ref["act_mpi"])
     say(f"  4^4 beta=5.6: act = {m:.5f}({e*1e5:.0f}); paper {ref['act_single']} Q={q1:.2f}, {ref['act_mpi']} Q={q2:.2f}")
+    # integrated autocorrelation time, per sweep and per measurement every nsw sweeps
+    t1, dt1, w1 = tau_int(s)
+    t2, dt2, w2 = tau_int(s[:: st["nsw"]])
+    say(f"  tau_int = {t1:.1f}({dt1:.1f}) sweeps (window {w1}), {t2:.1f}({dt2:.1f}) measurements every "
+        f"{st['nsw']} sweeps; the paper estimates 49.5(3.4)")
+    # the paper's estimate is in units of sweeps (reading R-TAU)
+    assert gaussian_difference_q(t1, dt1, *ref["tau_int"]) > QMIN
     assert max(q1, q2) > QMIN
+
+
+def full_statistics():
+    # eq. (1STAT): nequi sweeps, then nrpt * nmeas * nsw sweeps (measured
+    # here after every sweep)
+    st = GOLDEN["statistics_1STAT"]
+    return st["nequi"], st["nrpt"] * st["nmeas"] * st["nsw"]
 
 
 def test_paper_table1_8x8x8x4():
     ref = GOLDEN["pbc_8x8x8x4_b5.65"]
     lat = su3hb.Lattice(ref["extents"], start=su3hb.COLD, seed=6)
-    s = run_series(lat, ref["beta"], n_hit=1, ntherm=4096, nmeas=32 * 1024 * 2)
+    ntherm, nmeas = full_statistics()
+    s = run_series(lat, ref["beta"], n_hit=1, ntherm=ntherm, nmeas=nmeas)
     m, e = jackknife_mean(s, 32)
     qs = [gaussian_difference_q(m, e, *v) for v in ref["actm"]]
     say(f"  8^3 4 beta=5.65: act = {m:.6f}({e*1e6:.0f}); Q vs Table 1 rows = {[round(q, 2) for q in qs]}")
@@ -111,8 +141,9 @@ def test_paper_table1_8x8x8x4():
 def test_paper_table2_16x16x16x4():
     ref = GOLDEN["pbc_16x16x16x4_b5.65"]
     lat = su3hb.Lattice(ref["extents"], start=su3hb.COLD, seed=7)
-    lat.sweep(ref["beta"], n_hit=1, n_sweeps=4096)
-    ser = lat.sweep_measure(ref["beta"], n_hit=1, n_sweeps=32 * 1024 * 2)
+    ntherm, nmeas = full_statistics()
+    lat.sweep(ref["beta"], n_hit=1, n_sweeps=ntherm)
+    ser = lat.sweep_measure(ref["beta"], n_hit=1, n_sweeps=nmeas)
     ms, es = jackknife_mean(ser[:, 1], 32)
     mt, et = jackknife_mean(ser[:, 2], 32)
     qs = gaussian_difference_q(ms, es, *ref["spacelike_single"])
@@ -124,7 +155,8 @@ def test_paper_table2_16x16x16x4():
 def test_paper_table3_dlt_8x8x8x4():
     ref = GOLDEN["dlt_8x8x8x4_b5.55_disordered"]
     lat = su3hb.Lattice(ref["extents"], nlat=2, dlt_mask=0b1111, start=su3hb.HOT, seed=8)
-    s = run_series(lat, ref["beta"], n_hit=1, ntherm=4096, nmeas=32 * 512 * 2)
+    ntherm, nmeas = full_statistics()
+    s = run_series(lat, ref["beta"], n_hit=1, ntherm=ntherm, nmeas=nmeas)
     m, e = jackknife_mean(s, 32)
     qs = [gaussian_difference_q(m, e, *v) for v in ref["actm"]]
     say(f"  DLT 8^3 4 beta=5.55: act = {m:.6f}({e*1e6:.0f}); Q vs Table 3 rows = {[round(q, 2) for q in qs]}")

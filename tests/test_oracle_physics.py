@@ -6,7 +6,7 @@ import os
 import numpy as np
 import pytest
 
-from exact_su3 import u_exact
+from exact_su3 import dlt_two_coupling_exact, u_exact
 from stats import gaussian_difference_q, jackknife_mean
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
@@ -41,6 +41,24 @@ def test_2d_dlt_plaquette_exact(oracle_mod, mask):
     s = _series(L, 4.0, 8, 200, 4000)
     m, e = jackknife_mean(s, 32)
     assert abs(m - u_exact(4.0)) < 5 * e
+
+
+def test_2d_dlt_two_couplings_exact(oracle_mod):
+    # beta0 != beta1 on the 2D double-layered torus: per-layer averages and
+    # the beta-weighted sum against the exact values (pins the tag rule)
+    b0, b1 = 4.0, 2.0
+    L = oracle_mod.Lattice([8, 8], nlat=2, dlt_mask=0b11, seed=6, threads=2)
+    L.hot_start()
+    L.sweep(b0, b1, nhit=8, nsweeps=200)
+    rows = []
+    for _ in range(4000):
+        L.sweep(b0, b1, nhit=8, nsweeps=1)
+        rows.append(L.plaquette(b0, b1)[[3, 4, 5]])
+    rows = np.array(rows)
+    exact = dlt_two_coupling_exact(8, 8, b0, b1)
+    for k in range(3):
+        m, e = jackknife_mean(rows[:, k], 32)
+        assert abs(m - exact[k]) < 5 * e, (k, m, e, exact[k])
 
 
 def test_4d_strong_coupling(oracle_mod):
