@@ -33,14 +33,31 @@ __device__ __forceinline__ void block_sum(double v[NV])
     }
 }
 
-// One thread per site (`spt` sites per thread, strided by the block size):
-// the D(D-1)/2 plaquettes based at x,
+// Plane k of D(D-1)/2 as (mu, nu), mu < nu, in the order (0,1), (0,2), ...
+template <int D>
+__device__ __forceinline__ void plane_dirs(int k, int &mu, int &nu)
+{
+    mu = 0;
+    nu = 1;
+#pragma unroll
+    for (int m = 0, c = 0; m < D; ++m)
+#pragma unroll
+        for (int n = m + 1; n < D; ++n, ++c)
+            if (c == k) {
+                mu = m;
+                nu = n;
+            }
+}
+
+// One thread per (site, plane) item (`spt` items per thread, strided by the
+// block size; items plane-major, so a wave reads consecutive sites):
 // (1/3) Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = (1/3) Re Tr(T1 T2^dag)
 // with T1 = U_mu(x) U_nu(x+mu), T2 = U_nu(x) U_mu(x+nu); products in FP64.
 // Partial sums per block: [spacelike, timelike, layer0, layer1, beta-weighted].
 template <int D, int PREC>
 __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
 {
+    constexpr int NPL = D * (D - 1) / 2;
     const uint32_t lb = blockIdx.x;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (lb < a.total_blocks) {
@@ -50,11 +67,15 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
         const double beta0 = a.use_rep_beta ? rep.beta0 : a.beta0;
         const double beta1 = a.use_rep_beta ? rep.beta1 : a.beta1;
         void *links = const_cast<void *>(a.links);
+        // items can outnumber links ((D-1)/2 per link): 64-bit item index
         const uint32_t nsite = rep.nlat * rep.V;
-        const uint32_t first = (lb - rep.plq_block0) * blockDim.x * rep.plq_spt + threadIdx.x;
+        const uint64_t nitem = uint64_t(nsite) * uint64_t(NPL);
+        const uint64_t first = uint64_t(lb - rep.plq_block0) * blockDim.x * rep.plq_spt + threadIdx.x;
         for (uint32_t j = 0; j < rep.plq_spt; ++j) {
-            const uint32_t lt = first + j * blockDim.x;
-            if (lt >= nsite) break;
+            const uint64_t it = first + uint64_t(j) * blockDim.x;
+            if (it >= nitem) break;
+            const int k = int(it / nsite);
+            const uint32_t lt = uint32_t(it - uint64_t(k) * nsite);
             const uint32_t layer = lt >= rep.V ? 1u : 0u;
             const uint32_t rem = lt - layer * rep.V;
             const int p = rem >= rep.Vh ? 1 : 0;
@@ -62,32 +83,23 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
             Site<D> x;
             x.from_half(rep, h, p, layer);
             const int q = 1 - p;
-            double site_sum = 0.0;
-            // planes one at a time: unrolled, every load of the site would be
-            // hoisted together and the kernel would run at one wave per SIMD
-#pragma unroll 1
-            for (int mu = 0; mu < D; ++mu) {
-                const Step fm = step_fwd<D>(rep, x, mu, glued);
-                const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
-                const mat3<double> umx = widen<double>(
-                    load_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh));
-#pragma unroll 1
-                for (int nu = mu + 1; nu < D; ++nu) {
-                    const Step fn = step_fwd<D>(rep, x, nu, glued);
-                    const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
-                    const mat3<double> t1 = mul_nn(
-                        umx, widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh)));
-                    const mat3<double> t2 = mul_nn(
-                        widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, nu, p, x.s), rep.Vh)),
-                        widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh)));
-                    const double P = re_tr_na(t1, t2) * (1.0 / 3.0);
-                    if (nu == D - 1) v[1] += P; else v[0] += P;
-                    site_sum += P;
-                    const uint32_t tags = layer + l_pm + l_pn + layer;
-                    v[4] += (tags == 0 ? beta0 : beta1) * P;
-                }
-            }
-            if (layer == 0) v[2] += site_sum; else v[3] += site_sum;
+            int mu, nu;
+            plane_dirs<D>(k, mu, nu);
+            const Step fm = step_fwd<D>(rep, x, mu, glued);
+            const Step fn = step_fwd<D>(rep, x, nu, glued);
+            const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
+            const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
+            const mat3<double> t1 =
+                mul_nn(widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh)),
+                       widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh)));
+            const mat3<double> t2 =
+                mul_nn(widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, nu, p, x.s), rep.Vh)),
+                       widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh)));
+            const double P = re_tr_na(t1, t2) * (1.0 / 3.0);
+            if (nu == D - 1) v[1] += P; else v[0] += P;
+            if (layer == 0) v[2] += P; else v[3] += P;
+            const uint32_t tags = layer + l_pm + l_pn + layer;
+            v[4] += (tags == 0 ? beta0 : beta1) * P;
         }
     }
     block_sum<5>(v);

@@ -128,12 +128,14 @@ void layout_reps(su3hb_lattice *L)
         r.upd_block0 = ub;
         r.upd_blocks = (r.nlat * r.Vh + L->block - 1) / L->block;
         ub += r.upd_blocks;
-        // a few sites per plaquette thread keep the partial sums to about 4096
-        // blocks per lattice for the finalize pass
-        const uint32_t nsite = r.nlat * r.V;
-        r.plq_spt = std::min<uint32_t>(16, std::max<uint32_t>(1, nsite / (uint32_t(kPlaqBlock) * 4096u)));
+        // one plaquette thread item per (site, plane); a few items per thread
+        // keep the partial sums to about 4096 blocks per lattice for the
+        // finalize pass
+        const uint64_t nitem = uint64_t(r.nlat) * r.V * uint64_t(L->nd * (L->nd - 1) / 2);
+        r.plq_spt = uint32_t(std::min<uint64_t>(16, std::max<uint64_t>(1, nitem / (uint64_t(kPlaqBlock) * 4096u))));
         r.plq_block0 = pb;
-        r.plq_blocks = (nsite + kPlaqBlock * r.plq_spt - 1) / (kPlaqBlock * r.plq_spt);
+        const uint64_t per_block = uint64_t(kPlaqBlock) * r.plq_spt;
+        r.plq_blocks = uint32_t((nitem + per_block - 1) / per_block);
         pb += r.plq_blocks;
         r.pers_block0 = sb;
         r.pers_blocks = (r.nlat * r.Vh + kPersistentThreads - 1) / kPersistentThreads;
