@@ -108,54 +108,59 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
         for (int i = 0; i < 5; ++i) a.partials[size_t(lb) * 5 + i] = v[i];
 }
 
-// Fused measurement of a single-layer lattice: meas[mu][b] holds the block
-// sums of (1/3) Re Tr U_p over the planes (nu, mu), nu < mu, written by the
-// parity-1 update slices.  One block adds them up in a fixed order.
-__global__ void __launch_bounds__(1024) measure_finalize_kernel(const double *meas, int D, uint32_t nblocks,
-                                                                 double V, double beta0, double *out,
-                                                                 double *series, uint32_t *cursor)
+// Fused measurement: meas[mu][b][c] holds the block sums of (1/3) Re Tr U_p
+// over the planes (nu, mu), nu < mu, written by the parity-1 update slices,
+// in nc classes: nc = 1 for one layer; nc = 3 for two layers (0: base site in
+// layer 0 and all links in layer 0, 1: base in layer 0 otherwise, 2: base in
+// layer 1).  One block adds them up in a fixed order.
+__global__ void __launch_bounds__(1024) measure_finalize_kernel(const double *meas, int D, uint32_t nblocks, int nc,
+                                                                 double V, int nlat, double beta0, double beta1,
+                                                                 double *out, double *series, uint32_t *cursor)
 {
-    double v[2] = {0.0, 0.0};  // spacelike, timelike
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // [spacelike, timelike] x class
     const uint32_t bd = blockDim.x;
     for (int mu = 1; mu < D; ++mu) {
-        // eight independent partial sums (fixed assignment, so the result is
-        // reproducible) keep eight loads in flight per thread
-        const double *m = meas + size_t(mu) * nblocks;
-        double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        uint32_t b = threadIdx.x;
-        for (; b + 7 * bd < nblocks; b += 8 * bd) {
+        for (int c = 0; c < nc; ++c) {
+            // eight independent partial sums (fixed assignment, so the result
+            // is reproducible) keep eight loads in flight per thread
+            const double *m = meas + size_t(mu) * nblocks * nc + c;
+            double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            uint32_t b = threadIdx.x;
+            for (; b + 7 * bd < nblocks; b += 8 * bd) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) s[k] += m[b + k * bd];
+                for (int k = 0; k < 8; ++k) s[k] += m[size_t(b + k * bd) * nc];
+            }
+            for (; b < nblocks; b += bd) s[0] += m[size_t(b) * nc];
+            v[(mu == D - 1 ? 3 : 0) + c] += ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
         }
-        for (; b < nblocks; b += bd) s[0] += m[b];
-        v[mu == D - 1 ? 1 : 0] += ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        v[0] += __shfl_xor(v[0], off);
-        v[1] += __shfl_xor(v[1], off);
-    }
-    __shared__ double sh[16][2];
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[i] += __shfl_xor(v[i], off);
+    __shared__ double sh[16][6];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        sh[wave][0] = v[0];
-        sh[wave][1] = v[1];
-    }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sh[wave][i] = v[i];
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < int(blockDim.x >> 6); ++w) {
-            v[0] += sh[w][0];
-            v[1] += sh[w][1];
-        }
-        const double nspace = V * (D - 1) * (D - 2) / 2.0, ntime = V * (D - 1);
+        for (int w = 1; w < int(blockDim.x >> 6); ++w)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) v[i] += sh[w][i];
+        const double nV = double(nlat) * V;
+        const double nspace = nV * (D - 1) * (D - 2) / 2.0, ntime = nV * (D - 1);
+        const double nlayer = V * D * (D - 1) / 2.0;
         const double nan = __builtin_nan("");
+        const double space = v[0] + v[1] + v[2], time = v[3] + v[4] + v[5];
+        const double t0 = v[0] + v[3], t1 = v[1] + v[4], t2 = v[2] + v[5];
         double o[6];
-        o[0] = (v[0] + v[1]) / (nspace + ntime);
-        o[1] = nspace > 0 ? v[0] / nspace : nan;
-        o[2] = v[1] / ntime;
-        o[3] = o[0];
-        o[4] = nan;
-        o[5] = beta0 * (v[0] + v[1]);
+        o[0] = (space + time) / (nspace + ntime);
+        o[1] = nspace > 0 ? space / nspace : nan;
+        o[2] = time / ntime;
+        o[3] = (t0 + t1) / nlayer;
+        o[4] = nlat == 2 ? t2 / nlayer : nan;
+        o[5] = beta0 * t0 + beta1 * (t1 + t2);
         for (int i = 0; i < 6; ++i) out[i] = o[i];
         if (series) {
             const uint32_t k = atomicAdd(cursor, 1u);
@@ -164,11 +169,13 @@ __global__ void __launch_bounds__(1024) measure_finalize_kernel(const double *me
     }
 }
 
-hipError_t launch_measure_finalize(hipStream_t st, const double *meas, int D, uint32_t nblocks, double V,
-                                   double beta0, double *out, double *series, uint32_t *cursor)
+hipError_t launch_measure_finalize(hipStream_t st, const double *meas, int D, uint32_t nblocks, int nc, double V,
+                                   int nlat, double beta0, double beta1, double *out, double *series,
+                                   uint32_t *cursor)
 {
-    hipLaunchKernelGGL(measure_finalize_kernel, dim3(1), dim3(1024), 0, st, meas, D, nblocks, V, beta0, out,
-                       series, cursor);
+    if (nc != 1 && nc != 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(measure_finalize_kernel, dim3(1), dim3(1024), 0, st, meas, D, nblocks, nc, V, nlat, beta0,
+                       beta1, out, series, cursor);
     return hipGetLastError();
 }
 

@@ -341,6 +341,7 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
     }
     a.beta0 = b0;
     a.beta1 = b1;
+    a.meas_classes = 1;
     a.sweep = L->d_sweep;
     a.stats = L->d_stats;
     a.total_blocks = L->upd_blocks;
@@ -375,11 +376,16 @@ int enqueue_plaquette(su3hb_lattice *L, hipStream_t st, double b0, double b1, do
 // The plaquettes of a single-layer lattice are measured inside the parity-1
 // update slices (see update.hip); two layers and batches use the plaquette
 // kernel after the sweep.
-bool fused_measure(const su3hb_lattice *L) { return !L->batch && L->reps[0].nlat == 1; }
+// Single lattices (one or two layers) measure inside the parity-1 update
+// slices; batches use the plaquette kernel.
+bool fused_measure(const su3hb_lattice *L) { return !L->batch; }
+
+// Measurement classes: one layer 1; two layers 3 (by base layer and tags).
+int meas_classes(const su3hb_lattice *L) { return L->reps[0].nlat == 2 ? 3 : 1; }
 
 int ensure_meas(su3hb_lattice *L)
 {
-    const size_t need = size_t(L->nd) * L->upd_blocks;
+    const size_t need = size_t(L->nd) * L->upd_blocks * size_t(meas_classes(L));
     if (need <= L->meas_cap) return SU3HB_OK;
     hipFree(L->d_meas);
     L->d_meas = nullptr;
@@ -398,7 +404,10 @@ int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nh
 {
     UpdateArgs a = update_args(L, b0, b1, nhit);
     const bool fused = measure && fused_measure(L);
-    if (fused) a.meas = L->d_meas;
+    if (fused) {
+        a.meas = L->d_meas;
+        a.meas_classes = meas_classes(L);
+    }
     const dim3 grid = update_grid(L), block(L->block);
     for (int p = 0; p < 2; ++p)
         for (int mu = 0; mu < L->nd; ++mu) {
@@ -415,8 +424,8 @@ int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nh
     if (!measure) return SU3HB_OK;
     if (fused) {
         if (timed) HIPCHK(hipEventRecord(L->events[(*ev)++], st));
-        HIPCHK(launch_measure_finalize(st, L->d_meas, L->nd, L->upd_blocks, double(L->reps[0].V), b0, L->d_plaq,
-                                       L->d_series, L->d_cursor));
+        HIPCHK(launch_measure_finalize(st, L->d_meas, L->nd, L->upd_blocks, meas_classes(L), double(L->reps[0].V),
+                                       int(L->reps[0].nlat), b0, b1, L->d_plaq, L->d_series, L->d_cursor));
         if (timed) {
             HIPCHK(hipEventRecord(L->events[(*ev)++], st));
             timed->push_back(1);

@@ -372,18 +372,26 @@ __device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
 // of x is B3 of x + mu + nu), each pair issued back to back so that the
 // second read of a line finds it still in L2.  FP64-18 streams F2, B2, F1 and
 // B3 row by row to keep registers down; other modes load whole links.
-template <int PREC>
+//
+// CLASSES (a measured plane of a two-layer lattice): acc receives exactly the
+// same operations, and the unweighted forward term F1 (F3 F2)^dag and
+// backward term (B2 B1)^dag B3 are also added to the measurement classes cf
+// and cb, held in LDS as cls[(c * 9 + e) * stride + t] (slot t of class c,
+// element e).
+template <int PREC, bool CLASSES = false>
 __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
                                                   const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
                                                   const LinkRef &b2, const LinkRef &b3, uint32_t Vh,
-                                                  typename Store<PREC>::real wf, typename Store<PREC>::real wb)
+                                                  typename Store<PREC>::real wf, typename Store<PREC>::real wb,
+                                                  cx<typename Store<PREC>::real> *cls = nullptr,
+                                                  uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
 {
     using R = typename Store<PREC>::real;
     constexpr bool stream = PREC == kFP64_18;
     const mat3<R> m3 = load_link<PREC>(f3, Vh);
     const mat3<R> mb1 = load_link<PREC>(b1, Vh);
     // T_ij = wf conj(sum_k F3_jk F2_ki): row k of F2 adds to every T_ij
-    mat3<R> T;
+    mat3<R> T, Tu;
     set_zero(T);
     {
         mat3<R> m2;
@@ -398,13 +406,14 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
 #pragma unroll
                 for (int j = 0; j < 3; ++j) cfma_cn(T.e[i][j], m3.e[j][k], cx<R>{r2[i].re, -r2[i].im});
         }
+        if constexpr (CLASSES) Tu = T;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) T.e[i][j] = cx<R>{wf * T.e[i][j].re, wf * T.e[i][j].im};
     }
     // S_ij = wb conj(sum_k B2_jk B1_ki): row j of B2 gives column j of S
-    mat3<R> S;
+    mat3<R> S, Su;
     {
         mat3<R> mb2;
         if constexpr (!stream) mb2 = load_link<PREC>(b2, Vh);
@@ -419,11 +428,16 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
 #pragma unroll
                 for (int k = 0; k < 3; ++k) cfma(s, r2[k], mb1.e[k][i]);
                 S.e[i][j] = cx<R>{wb * s.re, -wb * s.im};
+                if constexpr (CLASSES) Su.e[i][j] = cx<R>{s.re, -s.im};
             }
         }
     }
     // acc += F1 T + S B3, F1 and B3 taken row by row together
-    mat3<R> m1, mb3;
+    mat3<R> m1, mb3, Fu, Bu;
+    if constexpr (CLASSES) {
+        set_zero(Fu);
+        set_zero(Bu);
+    }
     if constexpr (!stream) {
         m1 = load_link<PREC>(f1, Vh);
         mb3 = load_link<PREC>(b3, Vh);
@@ -439,11 +453,28 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) cfma(acc.e[r][j], r1[k], T.e[k][j]);
+            for (int k = 0; k < 3; ++k) {
+                cfma(acc.e[r][j], r1[k], T.e[k][j]);
+                if constexpr (CLASSES) cfma(Fu.e[r][j], r1[k], Tu.e[k][j]);
+            }
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) cfma(acc.e[i][j], S.e[i][r], r3[j]);
+            for (int j = 0; j < 3; ++j) {
+                cfma(acc.e[i][j], S.e[i][r], r3[j]);
+                if constexpr (CLASSES) cfma(Bu.e[i][j], Su.e[i][r], r3[j]);
+            }
+    }
+    if constexpr (CLASSES) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            cx<R> &fe = cls[(cf * 9 + e) * stride + t];
+            fe.re += Fu.e[e / 3][e % 3].re;
+            fe.im += Fu.e[e / 3][e % 3].im;
+            cx<R> &be = cls[(cb * 9 + e) * stride + t];
+            be.re += Bu.e[e / 3][e % 3].re;
+            be.im += Bu.e[e / 3][e % 3].im;
+        }
     }
 }
 

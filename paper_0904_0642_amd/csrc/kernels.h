@@ -23,10 +23,12 @@ hipError_t launch_plaquette_finalize(hipStream_t st, const RepDesc *reps, int nr
                                      const double *partials, double *out, double *series,
                                      uint32_t *series_cursor);
 
-// fused measurement of a single-layer lattice: sums the per-block plaquette
-// partials the parity-1 update slices wrote, normalises like the plaquette path
-hipError_t launch_measure_finalize(hipStream_t st, const double *meas, int D, uint32_t nblocks, double V,
-                                   double beta0, double *out, double *series, uint32_t *cursor);
+// fused measurement: sums the per-block plaquette class partials (nc = 1 for
+// one layer, 3 for two) the parity-1 update slices wrote, normalises like the
+// plaquette path
+hipError_t launch_measure_finalize(hipStream_t st, const double *meas, int D, uint32_t nblocks, int nc, double V,
+                                   int nlat, double beta0, double beta1, double *out, double *series,
+                                   uint32_t *cursor);
 
 // start configuration of one replica: mode 1 ordered, 2 Haar
 hipError_t launch_start(int D, int prec, hipStream_t st, void *links, const RepDesc *reps, int r,

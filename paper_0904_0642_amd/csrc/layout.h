@@ -81,7 +81,8 @@ struct UpdateArgs {
     const uint32_t *sweep;       // device sweep counter
     StatSlot *stats;             // kStatSlots slots
     uint32_t total_blocks;       // real blocks (grid may be padded to 8)
-    double *meas;                // fused plaquettes: [mu][total_blocks] partial sums, or null
+    double *meas;                // fused plaquettes: [mu][total_blocks][meas_classes] partial sums, or null
+    int meas_classes;            // 1: one lattice layer; 3: two layers (classes by base layer and tags)
     int persistent;              // 1: logical blocks of the persistent partition
     uint32_t *barrier;           // persistent launches: kBarrierWords counters, zeroed before the launch
 };

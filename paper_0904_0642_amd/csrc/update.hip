@@ -143,10 +143,17 @@ __device__ __forceinline__ void su2_reflect(mat3<H> &U, mat3<H> &W, int &attempt
 // every plaquette of such a plane holds exactly one odd-site U_mu link.  So
 // (1/3) Re Tr(U'_mu(x) A_{nu<mu}(x)) summed over the parity-1 slices counts
 // every plaquette of the end-of-sweep configuration exactly once.
-template <int D, int PREC>
+//
+// Two layers (NC = 3, a kernel instantiated for measured parity-1 slices of
+// two-layer lattices): the unweighted forward and backward terms of the
+// planes nu < mu go to three classes, by the layer of the plaquette's base
+// site and its tag sum: 0 = base in layer 0 with all links in layer 0 (beta0),
+// 1 = base in layer 0 otherwise (beta1), 2 = base in layer 1 (beta1), so that
+// the layer averages and the beta-weighted sum follow from the class sums.
+template <int D, int PREC, int NC>
 __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &rep, uint32_t lt,
                                             uint32_t sweep, int att[3], int acc[3], double &dtrace,
-                                            double &plaq)
+                                            double *plaq)
 {
     using R = typename Store<PREC>::real;
     const int p = a.parity, q = 1 - a.parity, mu = a.mu;
@@ -162,24 +169,34 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     const uint32_t glued = single ? 0u : rep.glued;
     const double beta0 = a.use_rep_beta ? rep.beta0 : a.beta0;
     const double beta1 = a.use_rep_beta ? rep.beta1 : a.beta1;
-    const bool measure = a.meas != nullptr && p == 1 && single;
+    const bool measure = a.meas != nullptr && p == 1 && (NC == 3 || single);
 
     // staple sum A = sum_{nu != mu} beta_f U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
     //                             + beta_b U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
     const Step fm = step_fwd<D>(rep, x, mu, glued);
     const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
-    // the unweighted sum of the planes nu < mu waits in this thread's slot of
-    // dynamic LDS (element-major, sized by the launch when measuring)
+    // the unweighted sum of the planes nu < mu (NC = 1), or its NC class
+    // sums, waits in this thread's slots of dynamic LDS (element-major, sized
+    // by the launch when measuring)
     extern __shared__ char s_dyn[];
     cx<R> *alow = reinterpret_cast<cx<R> *>(s_dyn);
+    const uint32_t bd = blockDim.x, tid = threadIdx.x;
+    if constexpr (NC == 3) {
+        if (measure) {
+#pragma unroll
+            for (int e = 0; e < 27; ++e) alow[e * bd + tid] = cx<R>{R(0), R(0)};
+        }
+    }
     mat3<R> A;
     set_zero(A);
 #pragma unroll
     for (int nu = 0; nu < D; ++nu) {
         if (nu == mu) {
-            if (measure) {
+            if constexpr (NC == 1) {
+                if (measure) {
 #pragma unroll
-                for (int e = 0; e < 9; ++e) alow[e * blockDim.x + threadIdx.x] = A.e[e / 3][e % 3];
+                    for (int e = 0; e < 9; ++e) alow[e * bd + tid] = A.e[e / 3][e % 3];
+                }
             }
             continue;
         }
@@ -191,6 +208,22 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
 
         const uint32_t tags_f = layer + l_pm + l_pn + layer;
         const uint32_t tags_b = l_mn + l_pmmn + layer + l_mn;
+        if constexpr (NC == 3) {
+            if (measure && nu < mu) {
+                const int cf = layer == 0 ? (tags_f == 0 ? 0 : 1) : 2;
+                const int cb = l_mn == 0 ? (tags_b == 0 ? 0 : 1) : 2;
+                acc_plane_staples<PREC, true>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm),
+                                              link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn),
+                                              link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
+                                              link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn),
+                                              link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn),
+                                              link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
+                                              single ? R(1) : R(tags_f == 0 ? beta0 : beta1),
+                                              single ? R(1) : R(tags_b == 0 ? beta0 : beta1), alow, bd, tid,
+                                              cf, cb);
+                continue;
+            }
+        }
         acc_plane_staples<PREC>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm),
                                 link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn),
                                 link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
@@ -224,19 +257,24 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     mat3<double> Ud = widen<double>(U);
     reunitarize(Ud);
     if (measure) {
-        mat3<R> Alow;
+        const mat3<double> Us = stored_form<PREC>(Ud);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) Alow.e[e / 3][e % 3] = alow[e * blockDim.x + threadIdx.x];
-        plaq = re_tr_nn(stored_form<PREC>(Ud), widen<double>(Alow)) * (1.0 / 3.0);
+        for (int c = 0; c < NC; ++c) {
+            mat3<R> M;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) M.e[e / 3][e % 3] = alow[(c * 9 + e) * bd + tid];
+            plaq[c] += re_tr_nn(Us, widen<double>(M)) * (1.0 / 3.0);
+        }
     }
     store_link<PREC>(uptr, Vh, Ud);
 }
 
 // Sum the per-thread counters over the block and add them to one slot; with
-// a fused measurement also store the block's plaquette sum (plain store, one
-// slot per (direction, block), added up later in a fixed order).
+// a fused measurement also store the block's NC plaquette class sums (plain
+// stores, one group per (direction, block), added up later in a fixed order).
+template <int NC>
 __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, int att[3], int acc[3], int upd,
-                                            double dtrace, double plaq)
+                                            double dtrace, double *plaq)
 {
     int v[7] = {att[0], att[1], att[2], acc[0], acc[1], acc[2], upd};
 #pragma unroll
@@ -244,16 +282,18 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
 #pragma unroll
         for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], off);
         dtrace += __shfl_xor(dtrace, off);
-        plaq += __shfl_xor(plaq, off);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) plaq[c] += __shfl_xor(plaq[c], off);
     }
     __shared__ int s_int[kPersistentThreads / 64][7];
-    __shared__ double s_dbl[kPersistentThreads / 64][2];
+    __shared__ double s_dbl[kPersistentThreads / 64][1 + NC];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < 7; ++i) s_int[wave][i] = v[i];
         s_dbl[wave][0] = dtrace;
-        s_dbl[wave][1] = plaq;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s_dbl[wave][1 + c] = plaq[c];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -262,7 +302,8 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
 #pragma unroll
             for (int i = 0; i < 7; ++i) v[i] += s_int[w][i];
             dtrace += s_dbl[w][0];
-            plaq += s_dbl[w][1];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) plaq[c] += s_dbl[w][1 + c];
         }
         StatSlot *sl = &a.stats[lb % kStatSlots];
 #pragma unroll
@@ -273,7 +314,8 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
         atomicAdd(&sl->updates, (unsigned long long)v[6]);
         unsafeAtomicAdd(&sl->dtrace, dtrace);
         if (a.meas != nullptr && a.parity == 1 && lb < a.total_blocks)
-            a.meas[size_t(a.mu) * a.total_blocks + lb] = plaq;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a.meas[(size_t(a.mu) * a.total_blocks + lb) * NC + c] = plaq[c];
     }
     __syncthreads();  // the shared arrays are reused by the next block in a persistent loop
 }
@@ -281,9 +323,9 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
 // Update the links of logical block lb (replica found by binary search),
 // adding to the thread's counters; lt_override >= 0 gives the thread's link
 // directly (order 3).
-template <int D, int PREC>
+template <int D, int PREC, int NC>
 __device__ __forceinline__ void block_links(const UpdateArgs &a, uint32_t lb, uint32_t sweep, int att[3], int acc[3],
-                                            int &upd, double &dtrace, double &plaq, int64_t lt_override = -1)
+                                            int &upd, double &dtrace, double *plaq, int64_t lt_override = -1)
 {
     if (lb < a.total_blocks) {
         const int kind = a.persistent ? kPersistentBlocks : kUpdateBlocks;
@@ -292,21 +334,23 @@ __device__ __forceinline__ void block_links(const UpdateArgs &a, uint32_t lb, ui
         const uint32_t lt = lt_override >= 0 ? uint32_t(lt_override)
                                              : (lb - first_block(rep, kind)) * blockDim.x + threadIdx.x;
         if (lt < rep.nlat * rep.Vh) {
-            update_link<D, PREC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
+            update_link<D, PREC, NC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
             ++upd;
         }
     }
 }
 
 // One logical block of a per-slice launch, its counters flushed at the end.
-template <int D, int PREC>
+template <int D, int PREC, int NC>
 __device__ __forceinline__ void process_block(const UpdateArgs &a, uint32_t lb, uint32_t sweep,
                                               int64_t lt_override = -1)
 {
     int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
-    double dtrace = 0.0, plaq = 0.0;
-    block_links<D, PREC>(a, lb, sweep, att, acc, upd, dtrace, plaq, lt_override);
-    flush_stats(a, lb, att, acc, upd, dtrace, plaq);
+    double dtrace = 0.0, plaq[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) plaq[c] = 0.0;
+    block_links<D, PREC, NC>(a, lb, sweep, att, acc, upd, dtrace, plaq, lt_override);
+    flush_stats<NC>(a, lb, att, acc, upd, dtrace, plaq);
 }
 
 // Logical block of hardware block b.  Hardware blocks are dealt round-robin
@@ -355,13 +399,13 @@ __device__ __forceinline__ uint32_t link_of_thread_3d(const UpdateArgs &a, uint3
     return (x2 + a.n2 * x3) * a.plane + c * 64u + lane;
 }
 
-template <int D, int PREC, int WAVES>
+template <int D, int PREC, int WAVES, int NC = 1>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
     if (a.order == 3)
-        process_block<D, PREC>(a, blockIdx.x, *a.sweep, int64_t(link_of_thread_3d(a, blockIdx.x)));
+        process_block<D, PREC, NC>(a, blockIdx.x, *a.sweep, int64_t(link_of_thread_3d(a, blockIdx.x)));
     else
-        process_block<D, PREC>(a, logical_block(a, blockIdx.x), *a.sweep);
+        process_block<D, PREC, NC>(a, logical_block(a, blockIdx.x), *a.sweep);
 }
 
 // Grid barrier of a persistent launch (all blocks resident: cooperative
@@ -432,10 +476,10 @@ __global__ void __launch_bounds__(THREADS, THREADS / 256) update_persistent_kern
                 // the waves of the block run freely over the slice; counters
                 // are flushed once per slice, next to the barrier's own sync
                 int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
-                double dtrace = 0.0, plaq = 0.0;
+                double dtrace = 0.0, plaq[1] = {0.0};
                 for (uint32_t lb = first; lb < last; lb += step)
-                    block_links<D, PREC>(b, lb, sweep0 + uint32_t(sw), att, acc, upd, dtrace, plaq);
-                flush_stats(b, blockIdx.x, att, acc, upd, dtrace, plaq);
+                    block_links<D, PREC, 1>(b, lb, sweep0 + uint32_t(sw), att, acc, upd, dtrace, plaq);
+                flush_stats<1>(b, blockIdx.x, att, acc, upd, dtrace, plaq);
                 if (!grid_barrier(a.barrier, gen++)) return;
             }
         }
@@ -448,13 +492,20 @@ template <int PREC>
 static size_t update_lds_bytes(dim3 block, const UpdateArgs &a)
 {
     using R = typename Store<PREC>::real;
-    return (a.meas != nullptr && a.parity == 1) ? size_t(block.x) * 9 * sizeof(cx<R>) : 0;
+    return (a.meas != nullptr && a.parity == 1) ? size_t(block.x) * 9 * a.meas_classes * sizeof(cx<R>) : 0;
 }
 
 template <int D, int PREC>
 static hipError_t launch_update_t(int waves, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
 {
     const size_t lds = update_lds_bytes<PREC>(block, a);
+    if (a.meas != nullptr && a.parity == 1 && a.meas_classes == 3) {
+        // measured slice of a two-layer lattice: the class-splitting kernel
+        hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves, 3>), grid, block, lds, st, a);
+        return hipGetLastError();
+    }
+    // parity-0 slices of a measured sweep measure nothing and use this kernel
+    if (a.meas != nullptr && a.meas_classes != 1 && a.meas_classes != 3) return hipErrorInvalidValue;
     if constexpr (D == 4) {
         if (waves == 3) {
             hipLaunchKernelGGL((update_kernel<D, PREC, 3>), grid, block, lds, st, a);

@@ -293,6 +293,33 @@ def test_overrelaxation_graphs_equal_direct_launches():
     assert a.get_state() == b.get_state()
 
 
+@pytest.mark.parametrize("ext,mask,b0,b1,prec,tol", [
+    ([4, 6, 4, 2], 0b1111, 5.5, 6.2, su3hb.FP64_18, 1e-13),
+    ([8, 8, 4, 4], 0b0111, 5.9, 5.9, su3hb.FP64_18, 1e-13),
+    ([6, 4, 8], 0b101, 5.0, 6.5, su3hb.FP64_12, 1e-13),
+    ([16, 8], 0b11, 4.0, 2.0, su3hb.FP64_18, 1e-13),
+    ([8, 8, 8, 4], 0b1111, 5.55, 5.55, su3hb.FP32_18, 2e-6),
+    ([8, 8, 4, 4], 0b1000, 5.6, 6.0, su3hb.FP32_12, 2e-6)])
+def test_fused_measurement_two_layers(ext, mask, b0, b1, prec, tol):
+    # two layers: the parity-1 slices sort the plaquette terms into three
+    # classes (base layer, tag sum); totals, spacelike/timelike, per layer and
+    # the beta-weighted sum equal the standalone kernel on the same links
+    a = su3hb.Lattice(ext, nlat=2, dlt_mask=mask, seed=23, precision=prec)
+    b = su3hb.Lattice(ext, nlat=2, dlt_mask=mask, seed=23, precision=prec)
+    fused = a.sweep_measure(b0, b1, n_hit=8, n_sweeps=4)
+    sep = []
+    for _ in range(4):
+        b.sweep(b0, b1, n_hit=8, n_sweeps=1)
+        sep.append(b.plaquette(b0, b1))
+    sep = np.array(sep)
+    assert np.array_equal(a.get_links(), b.get_links())
+    assert np.array_equal(np.isnan(fused), np.isnan(sep))
+    good = ~np.isnan(sep)
+    d = np.abs(fused[good] - sep[good]) / np.maximum(1.0, np.abs(sep[good]))
+    say(f"  two layers ext={ext} mask={mask:b} beta=({b0},{b1}) prec={prec}: max rel diff = {d.max():.3e}")
+    assert d.max() <= tol
+
+
 def test_resume_is_bitwise(oracle_mod):
     a = su3hb.Lattice([8, 4, 4, 4], seed=21)
     a.sweep(5.8, n_hit=8, n_sweeps=6)
