@@ -234,15 +234,15 @@ def dlt_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int):
     return res
 
 
-def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
+def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 2000):
     """Equal-volume comparison at equal sweep count (hence equal statistical
-    error of <P>): 32^4 at beta = 6.0, same seed, FP64-18 / FP64-12 / FP32-18 / FP32-12."""
+    error of <P>, the algorithm and its autocorrelations being the same): 32^4
+    at beta = 6.0, same seed, FP64-18 / FP64-12 / FP32-18 / FP32-12.  Errors
+    from 20 jackknife bins of nmeas / 20 sweeps, longer than tau_int."""
     import torch
 
     import paper_0904_0642_amd as su3hb
-
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from stats import jackknife_mean
+    from paper_0904_0642_amd.analysis import jackknife_mean, tau_int
 
     ext, beta = (32, 32, 32, 32), 6.0
     links = int(np.prod(ext)) * 4
@@ -256,7 +256,9 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 400):
         ser = lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=nmeas)
         secs = time.perf_counter() - t0
         m, e = jackknife_mean(ser[:, 0], 20)
-        res[PREC_NAME[prec]] = {"rate": round(nmeas * links / secs, 1), "plaquette": m, "error": e}
+        tau, dtau, _ = tau_int(ser[:, 0])
+        res[PREC_NAME[prec]] = {"rate": round(nmeas * links / secs, 1), "plaquette": m, "error": e,
+                                "tau_int_sweeps": [round(tau, 1), round(dtau, 1)]}
         lat.close()
         torch.cuda.empty_cache()
     ref = res["fp64-18"]

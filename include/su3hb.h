@@ -164,7 +164,9 @@ int su3hb_set_links(su3hb_lattice *lat, const double *host, size_t n);
 
 /* Seed and sweep counter: with the links they are the whole Markov-chain
  * state, so get_links + get_state ... set_links + set_state resumes a run
- * exactly (the random numbers are a function of seed, sweep and link). */
+ * exactly (the random numbers are a function of seed, sweep and link).  The
+ * sweep index of the Philox counter is 32 bits: set_state rejects sweep >=
+ * 2^32 and a sweep call that would pass 2^32 returns SU3HB_EINVAL. */
 int su3hb_get_state(const su3hb_lattice *lat, uint64_t *seed, uint64_t *sweep);
 int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
 

@@ -245,7 +245,7 @@ void destroy(su3hb_lattice *L)
 {
     if (!L) return;
     hipSetDevice(L->device);
-    if (L->stream) hipStreamSynchronize(L->stream);
+    hipStreamSynchronize(L->stream);   // also the null stream: nothing may still run on this memory
     drop_graph(L);
     for (auto e : L->events) hipEventDestroy(e);
     if (L->owns_links && L->links) hipFree(L->links);
@@ -387,6 +387,9 @@ int ensure_meas(su3hb_lattice *L)
 {
     const size_t need = size_t(L->nd) * L->upd_blocks * size_t(meas_classes(L));
     if (need <= L->meas_cap) return SU3HB_OK;
+    // captured sweeps hold the old buffer's address
+    HIPCHK(hipStreamSynchronize(L->stream));
+    drop_graph(L);
     hipFree(L->d_meas);
     L->d_meas = nullptr;
     L->meas_cap = 0;
@@ -496,9 +499,19 @@ int get_graph(su3hb_lattice *L, double b0, double b1, int nhit, int measure, hip
     return SU3HB_OK;
 }
 
+// The device counter (the Philox sweep word) is 32 bits: refuse to wrap it.
+int check_sweep_room(const su3hb_lattice *L, int n)
+{
+    if (L->sweep + uint64_t(n < 0 ? 0 : n) > (uint64_t(1) << 32))
+        return fail(SU3HB_EINVAL, "sweep %llu + %d passes 2^32: the Philox counter holds a 32-bit sweep index",
+                    (unsigned long long)L->sweep, n);
+    return SU3HB_OK;
+}
+
 int run_sweeps(su3hb_lattice *L, double b0, double b1, int nhit, int n, int measure)
 {
     if (n <= 0) return SU3HB_OK;
+    if (int rc = check_sweep_room(L, n)) return rc;
     if (measure && fused_measure(L)) {
         int rc = ensure_meas(L);
         if (rc) return rc;
@@ -812,6 +825,9 @@ int su3hb_set_state(su3hb_lattice *L, uint64_t seed, uint64_t sweep)
 {
     if (!L) return fail(SU3HB_EINVAL, "lattice is NULL");
     if (L->batch) return fail(SU3HB_EINVAL, "batches keep one seed per replica");
+    if (sweep >= (uint64_t(1) << 32))
+        return fail(SU3HB_EINVAL, "sweep = %llu: the Philox counter holds a 32-bit sweep index",
+                    (unsigned long long)sweep);
     HIPCHK(hipSetDevice(L->device));
     L->seed = seed;
     L->reps[0].key0 = uint32_t(seed);
@@ -936,6 +952,7 @@ int su3hb_sweep_timed(su3hb_lattice *L, double beta0, double beta1, int n_hit, i
     if (measure && n_sweeps > int(kSeriesCap))
         return fail(SU3HB_EINVAL, "at most %u measured sweeps per call", kSeriesCap);
     int rc = check_sweep_args(beta0, beta1, n_hit == 0 ? 1 : n_hit, n_sweeps);  // 0: overrelaxation
+    if (!rc) rc = check_sweep_room(L, n_sweeps);
     if (rc) return rc;
     HIPCHK(hipSetDevice(L->device));
     if (measure && fused_measure(L)) {
@@ -1045,6 +1062,7 @@ int su3hb_batch_sweep(su3hb_batch *L, int n_hit, int n_sweeps, int mode, su3hb_s
     } else if (n_sweeps > 0) {
         // one resident block per CU (as many as fit), slices separated by a
         // grid barrier; a barrier that gives up raises a flag checked below
+        if (int rc2 = check_sweep_room(L, n_sweeps)) return rc2;
         int per_cu = 0;
         HIPCHK(persistent_max_blocks(L->nd, L->prec, &per_cu));
         if (per_cu < 1) return fail(SU3HB_EUNSUPPORTED, "persistent kernel cannot be resident");

@@ -214,6 +214,18 @@ def test_sweep_argument_errors():
         g.sweep(float("nan"))
     g.sweep(6.0, n_sweeps=0)
     assert g.get_state()[1] == 0
+    # the Philox sweep index is 32 bits: no state past it, no sweep across it
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        g.set_state(3, 2 ** 32)
+    assert ei.value.code == su3hb.EINVAL
+    g.set_state(3, 2 ** 32 - 1)
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        g.sweep(6.0, n_sweeps=2)
+    assert ei.value.code == su3hb.EINVAL
+    with pytest.raises(su3hb.SU3HBError):
+        g.overrelax(6.0, n_sweeps=2)
+    g.sweep(6.0, n_sweeps=1)
+    assert g.get_state() == (3, 2 ** 32)
 
 
 def test_zero_beta_is_degenerate(oracle_mod):
