@@ -258,7 +258,9 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 2000):
         m, e = jackknife_mean(ser[:, 0], 20)
         tau, dtau, _ = tau_int(ser[:, 0])
         res[PREC_NAME[prec]] = {"rate": round(nmeas * links / secs, 1), "plaquette": m, "error": e,
-                                "tau_int_sweeps": [round(tau, 1), round(dtau, 1)]}
+                                "tau_int_sweeps": [round(tau, 1), round(dtau, 1)],
+                                "spacelike": list(jackknife_mean(ser[:, 1], 20)),
+                                "timelike": list(jackknife_mean(ser[:, 2], 20))}
         lat.close()
         torch.cuda.empty_cache()
     ref = res["fp64-18"]
@@ -266,6 +268,9 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 2000):
         r = res[k]
         r["speedup_vs_fp64_at_equal_error"] = round(r["rate"] / ref["rate"], 3)
         r["delta_vs_fp64_in_sigma"] = round((r["plaquette"] - ref["plaquette"]) / np.hypot(r["error"], ref["error"]), 2)
+        for obs in ("spacelike", "timelike"):
+            (m, e), (m0, e0) = r[obs], ref[obs]
+            r[obs + "_delta_vs_fp64_in_sigma"] = round((m - m0) / np.hypot(e, e0), 2)
     return res
 
 

@@ -332,6 +332,24 @@ def test_fused_measurement_two_layers(ext, mask, b0, b1, prec, tol):
     assert d.max() <= tol
 
 
+def test_fp64_12_chain_equals_fp64_18():
+    # 12-real FP64 storage rebuilds row 2 with the same cross product that
+    # reunitarisation used to write it, so it loses nothing: the FP64-12
+    # chain equals the FP64-18 chain bit for bit (heatbath, overrelaxation,
+    # measurement)
+    a = su3hb.Lattice([8, 6, 4, 4], seed=44, precision=su3hb.FP64_18)
+    b = su3hb.Lattice([8, 6, 4, 4], seed=44, precision=su3hb.FP64_12)
+    assert np.array_equal(a.get_links(), b.get_links())
+    sa = a.sweep_measure(5.8, n_hit=8, n_sweeps=3)
+    sb = b.sweep_measure(5.8, n_hit=8, n_sweeps=3)
+    a.overrelax(5.8, n_sweeps=2)
+    b.overrelax(5.8, n_sweeps=2)
+    a.sweep(5.8, n_hit=8, n_sweeps=2)
+    b.sweep(5.8, n_hit=8, n_sweeps=2)
+    assert np.array_equal(a.get_links(), b.get_links())
+    assert np.array_equal(sa, sb, equal_nan=True)
+
+
 def test_resume_is_bitwise(oracle_mod):
     a = su3hb.Lattice([8, 4, 4, 4], seed=21)
     a.sweep(5.8, n_hit=8, n_sweeps=6)

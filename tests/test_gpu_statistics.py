@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import paper_0904_0642_amd as su3hb
+from paper_0904_0642_amd import workloads
 from exact_su3 import dlt_two_coupling_exact, u_exact
 from stats import gaussian_difference_q, jackknife_mean, tau_int
 
@@ -163,6 +164,30 @@ def test_paper_table3_dlt_8x8x8x4():
     assert max(qs) > QMIN
 
 
+def test_batched_fp32_replicas_reproduce_table1():
+    # the batched form: 64 independent FP32-18 replicas of the Table 1 lattice
+    # (8^3 4, beta = 5.65, ordered starts, own seeds) in one batch; the
+    # replica means are independent, so their spread gives the error of the
+    # ensemble mean, compared with the FP64 numbers of Table 1
+    ref = GOLDEN["pbc_8x8x8x4_b5.65"]
+    nrep = 64
+    seeds = workloads.seeds(nrep, seed=2024)
+    reps = [(tuple(ref["extents"]), ref["beta"], sd, su3hb.COLD) for sd in seeds]
+    b = su3hb.Batch(4, reps, precision=su3hb.FP32_18)
+    b.sweep(n_hit=1, n_sweeps=1000, mode=0)
+    acc = np.zeros(nrep)
+    nmeas = 1000
+    for _ in range(nmeas):
+        b.sweep(n_hit=1, n_sweeps=2, mode=0)
+        acc += b.plaquette()[:, 0]
+    means = acc / nmeas
+    m, e = means.mean(), means.std(ddof=1) / np.sqrt(nrep)
+    qs = [gaussian_difference_q(m, e, *v) for v in ref["actm"]]
+    say(f"  batch of {nrep} FP32 replicas 8^3 4 beta=5.65: act = {m:.6f}({e*1e6:.0f}); "
+        f"Q vs Table 1 rows = {[round(q, 2) for q in qs]}")
+    assert qs[0] > QMIN
+
+
 def test_long_run_gpu_vs_oracle(oracle_mod):
     # 4^4, beta = 6.0, ordered start, n_hit = 8 (the small workload): the GPU
     # chain and an independent oracle chain (other seed) agree statistically
@@ -194,14 +219,20 @@ def test_acceptance_near_97_percent():
 
 def test_fp32_vs_fp64_same_plaquette():
     # FP32 link storage (FP64 heatbath, reunitarisation, accumulation) gives
-    # the same <P> as FP64 within the statistical error of equal-length runs
+    # the same observables as FP64 within the statistical error of
+    # equal-length runs: total, spacelike and timelike plaquette and the
+    # action sum beta sum_p (1/3) Re Tr U_p
+    names = ("total", "spacelike", "timelike", "action")
+    cols = (0, 1, 2, 5)
     res = {}
     for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
         lat = su3hb.Lattice([16, 16, 16, 16], seed=10, precision=prec)
-        s = run_series(lat, 6.0, ntherm=300, nmeas=3000)
-        res[prec] = jackknife_mean(s, 32)
-    (m64, e64) = res[su3hb.FP64_18]
+        lat.sweep(6.0, n_hit=8, n_sweeps=300)
+        ser = lat.sweep_measure(6.0, n_hit=8, n_sweeps=3000)
+        res[prec] = [jackknife_mean(ser[:, c], 32) for c in cols]
     for prec in (su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
-        m, e = res[prec]
-        say(f"  16^4 beta=6.0 prec={prec}: {m:.6f}({e*1e6:.0f}) vs FP64 {m64:.6f}({e64*1e6:.0f})")
-        assert abs(m - m64) < 3 * np.hypot(e, e64)
+        for k, name in enumerate(names):
+            (m, e), (m64, e64) = res[prec][k], res[su3hb.FP64_18][k]
+            say(f"  16^4 beta=6.0 prec={prec} {name}: {m:.8g}({e:.2g}) vs FP64 {m64:.8g}({e64:.2g}), "
+                f"{(m - m64) / np.hypot(e, e64):+.2f} sigma")
+            assert abs(m - m64) < 3 * np.hypot(e, e64)
