@@ -70,9 +70,10 @@ typedef struct su3hb_params {
     int extents[SU3HB_MAX_D];      /* n^1 .. n^D, each even and >= 2 (Sec. 2) */
     int nlat;                      /* 1 = torus, 2 = double-layered torus     */
     unsigned dlt_mask;             /* nlat = 2: bit d set = direction d glued
-                                      to the other layer (Sec. 2.2, "all or
-                                      just volume directions"); 0 = two
-                                      independent tori.  Must be 0 if nlat=1. */
+                                      to the other layer (Sec. 2.2 glues every
+                                      direction or the spatial ones only); 0 =
+                                      two independent tori.  Must be 0 if
+                                      nlat=1.                                  */
     int lat2test;                  /* nlat = 2 only: both layers draw the same
                                       random numbers (Sec. 3.4)               */
     int precision;                 /* su3hb_precision                          */

@@ -208,7 +208,7 @@ def test_long_run_gpu_vs_oracle(oracle_mod):
 
 
 def test_acceptance_near_97_percent():
-    # Sec. 2.1: the 1-hit acceptance is around 97% in the scaling region
+    # Sec. 2.1 puts the single-hit acceptance near 97% at the couplings of interest
     lat = su3hb.Lattice([16, 16, 16, 16], seed=9)
     lat.sweep(6.0, n_hit=1, n_sweeps=100)
     st = lat.sweep(6.0, n_hit=1, n_sweeps=20, stats=True)

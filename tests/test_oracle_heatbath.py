@@ -17,7 +17,7 @@ def test_kp_single_hit_acceptance(oracle_mod, alpha):
 
 
 def test_kp_acceptance_matches_paper_ballpark():
-    # Sec. 2.1: 1-hit acceptance around 97% in the scaling region; alpha = 2k/3
+    # Sec. 2.1 puts the single-hit acceptance near 97% at the couplings of interest; alpha = 2k/3
     # with k ~ 2(D-1) beta * <P> ~ 6 * 6 * 0.6 gives alpha ~ 14.
     assert 0.96 < kp_acceptance(14.0) < 0.98
 
