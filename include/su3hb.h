@@ -99,7 +99,11 @@ typedef struct su3hb_stats {
 
 typedef struct su3hb_lattice su3hb_lattice;
 
-/* Bytes of device memory the links of `p` occupy (nlat*V*D*bytes-per-link). */
+/* Bytes of device memory the links of `p` occupy: nlat*D*2 slabs of V/2
+ * links, each slab rounded up to whole tiles of 64 links, times the bytes of
+ * one link (144, 96, 72 or 48).  The layout inside is the library's own;
+ * su3hb_get_links / su3hb_set_links convert to and from the canonical
+ * order. */
 int su3hb_links_bytes(const su3hb_params *p, size_t *bytes);
 
 /* Validate `p`, allocate or adopt the link buffer, and write the start
@@ -180,9 +184,12 @@ int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
  * directions (2 x 2 waves for 256 threads, 1 x 2 for 128; needs planes of a
  * multiple of 64 half-sites); 4 = as 2, walking the block's chunk of the
  * plane slowest and x_{D-2} in the middle.  Where an order does not apply
- * a lower one that does is used (4 and 2 fall back to 1, 3 to 2 or 1).  waves: minimum waves per SIMD the kernel is
- * compiled for: 2; 3 for D = 4; 4 for D = 4 with FP32 links.  Results are
- * bit-identical for every shape.  get_launch reports the order in effect. */
+ * a lower one that does is used (4 and 2 fall back to 1, 3 to 2 or 1).
+ * Adding 8 to an order makes every second slice of a sweep walk each XCD's
+ * blocks last to first, so a slice starts on the links the slice before it
+ * read last.  waves: minimum waves per SIMD the kernel is compiled for: 2;
+ * 3 for D = 4; 4 for D = 4 with FP32 links.  Results are bit-identical for
+ * every shape.  get_launch reports the order in effect (with the 8). */
 int su3hb_set_launch(su3hb_lattice *lat, int block, int order, int waves);
 int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *order, int *waves);
 

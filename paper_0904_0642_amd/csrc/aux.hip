@@ -90,11 +90,11 @@ __global__ void __launch_bounds__(256) plaquette_kernel(PlaqArgs a)
             const uint32_t s_pm = x.s + uint32_t(fm.ds), l_pm = layer ^ fm.flip;
             const uint32_t s_pn = x.s + uint32_t(fn.ds), l_pn = layer ^ fn.flip;
             const mat3<double> t1 =
-                mul_nn(widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh)),
-                       widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pm, nu, q, s_pm), rep.Vh)));
+                mul_nn(widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s))),
+                       widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pm, nu, q, s_pm))));
             const mat3<double> t2 =
-                mul_nn(widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, nu, p, x.s), rep.Vh)),
-                       widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pn, mu, q, s_pn), rep.Vh)));
+                mul_nn(widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, layer, nu, p, x.s))),
+                       widen<double>(load_link<PREC>(link_ref<D, PREC>(links, rep, l_pn, mu, q, s_pn))));
             const double P = re_tr_na(t1, t2) * (1.0 / 3.0);
             if (nu == D - 1) v[1] += P; else v[0] += P;
             if (layer == 0) v[2] += P; else v[3] += P;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) start_kernel(void *links, const RepDesc *
         }
         reunitarize(u);
     }
-    store_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), rep.Vh, u);
+    store_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, x.s), u);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(256) pack_kernel(const void *links, const RepD
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         const mat3<double> u = widen<double>(
-            load_link<PREC>(link_ref<D, PREC>(const_cast<void *>(links), rep, layer, mu, p, s), rep.Vh));
+            load_link<PREC>(link_ref<D, PREC>(const_cast<void *>(links), rep, layer, mu, p, s)));
         double *o = dst + (size_t(t) * D + mu) * 18;
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(256) unpack_kernel(void *links, const RepDesc 
         mat3<double> u;
 #pragma unroll
         for (int e = 0; e < 9; ++e) u.e[e / 3][e % 3] = cx<double>{in[2 * e], in[2 * e + 1]};
-        store_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, s), rep.Vh, u);
+        store_link<PREC>(link_ref<D, PREC>(links, rep, layer, mu, p, s), u);
     }
 }
 

@@ -124,7 +124,7 @@ void layout_reps(su3hb_lattice *L)
     const int NE = elems_per_link(L->prec);
     for (auto &r : L->reps) {
         r.elem_offset = off;
-        off += uint64_t(r.nlat) * L->nd * NE * r.V;
+        off += uint64_t(r.nlat) * L->nd * NE * 2 * r.Vhp;
         r.upd_block0 = ub;
         r.upd_blocks = (r.nlat * r.Vh + L->block - 1) / L->block;
         ub += r.upd_blocks;
@@ -182,6 +182,7 @@ RepDesc make_rep(int nd, const int *ext, int nlat, unsigned glued, int lat2test,
     }
     r.V = st;
     r.Vh = st / 2;
+    r.Vhp = padded_half(r.Vh);
     r.nlat = uint32_t(nlat);
     r.glued = glued;
     r.lat2test = uint32_t(lat2test);
@@ -221,7 +222,7 @@ int alloc_common(su3hb_lattice *L)
 int adopt_or_alloc_links(su3hb_lattice *L, void *borrowed, size_t borrowed_bytes)
 {
     uint64_t elems = 0;
-    for (auto &r : L->reps) elems += uint64_t(r.nlat) * L->nd * elems_per_link(L->prec) * r.V;
+    for (auto &r : L->reps) elems += uint64_t(r.nlat) * L->nd * elems_per_link(L->prec) * 2 * r.Vhp;
     L->links_bytes = size_t(elems) * bytes_per_elem(L->prec);
     if (borrowed) {
         if (borrowed_bytes < L->links_bytes)
@@ -308,12 +309,19 @@ bool cube_order_ok(const su3hb_lattice *L, int block)
     return plane % 64u == 0 && n2 % t2 == 0 && nl % (8u * t3) == 0;
 }
 
-int effective_order(const su3hb_lattice *L)
+// Flag added to an order: alternate slices walk every XCD's blocks backwards.
+constexpr int kOrderReverse = 8;
+
+// Block order in effect, without the reverse flag.
+int base_order(const su3hb_lattice *L)
 {
-    if (L->order == 3 && !cube_order_ok(L, L->block)) return slab_order_ok(L, L->block) ? 2 : 1;
-    if ((L->order == 2 || L->order == 4) && !slab_order_ok(L, L->block)) return 1;
-    return L->order;
+    const int o = L->order & ~kOrderReverse;
+    if (o == 3 && !cube_order_ok(L, L->block)) return slab_order_ok(L, L->block) ? 2 : 1;
+    if ((o == 2 || o == 4) && !slab_order_ok(L, L->block)) return 1;
+    return o;
 }
+
+int effective_order(const su3hb_lattice *L) { return base_order(L) | (L->order & kOrderReverse); }
 
 UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
 {
@@ -324,7 +332,7 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
     a.nrep = L->nrep;
     a.nhit = nhit;
     a.use_rep_beta = L->batch ? 1 : 0;
-    a.order = effective_order(L);
+    a.order = base_order(L);
     if (a.order >= 2) {
         const RepDesc &r = L->reps[0];
         const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
@@ -351,7 +359,7 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
 dim3 update_grid(const su3hb_lattice *L)
 {
     uint32_t g = L->upd_blocks;
-    if (effective_order(L) == 1) g = (g + 7) / 8 * 8;
+    if (base_order(L) == 1) g = (g + 7) / 8 * 8;
     return dim3(g);
 }
 
@@ -416,6 +424,7 @@ int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nh
         for (int mu = 0; mu < L->nd; ++mu) {
             a.parity = p;
             a.mu = mu;
+            a.reverse = (L->order & kOrderReverse) && ((p * L->nd + mu) & 1) ? 1 : 0;
             if (timed) HIPCHK(hipEventRecord(L->events[(*ev)++], st));
             HIPCHK(launch_update(L->nd, L->prec, L->waves, grid, block, st, a));
             if (timed) {
@@ -640,7 +649,8 @@ int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
-    if (order < 0 || order > 4) return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 4", order);
+    if (order < 0 || (order & ~kOrderReverse) > 4)
+        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 4, optionally + %d", order, kOrderReverse);
     if (waves != 2 && !(waves == 3 && L->nd == 4) && !(waves == 4 && L->nd == 4 && is_fp32(L->prec)))
         return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4, or 4 for D = 4 with FP32 links", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -678,7 +688,8 @@ int su3hb_links_bytes(const su3hb_params *p, size_t *bytes)
     if (rc) return rc;
     if (p->nlat != 1 && p->nlat != 2) return fail(SU3HB_EINVAL, "nlat = %d, expected 1 or 2", p->nlat);
     if (p->precision < 0 || p->precision > 3) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
-    *bytes = size_t(p->nlat) * p->nd * V * size_t(bytes_per_link(p->precision));
+    // two slabs (parities) of whole tiles per layer and direction
+    *bytes = size_t(p->nlat) * p->nd * 2 * size_t(padded_half(uint32_t(V / 2))) * size_t(bytes_per_link(p->precision));
     return SU3HB_OK;
 }
 
@@ -890,6 +901,7 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
                 if ((order == 2 || order == 4) && !slab_order_ok(L, block)) continue;
                 if (order == 3 && (block == 64 || !cube_order_ok(L, block))) continue;
                 cands.push_back(Shape{block, order, waves});
+                cands.push_back(Shape{block, order | kOrderReverse, waves});
             }
     }
     const double b = L->batch ? 0.0 : 6.0;

@@ -242,11 +242,14 @@ constexpr uint32_t kTagStart = 1;
 
 // ---------------------------------------------------------------------------
 // Link storage.  Per replica the links form slabs [layer][mu][parity], each
-// holding the Vh links of one direction and parity as structure-of-arrays
-// over the half-lattice index h, so a wave reads consecutive h contiguously:
-//   FP64: one double2 (one complex element) per array, NE arrays;
-//   FP32: elements paired into float4 arrays (2 complex per 16-byte load),
-//         plus one float2 array for the odd element of 18-real storage.
+// holding the links of one direction and parity, ordered by the half-lattice
+// index h and cut into tiles of kTile consecutive h.  A tile stores 16-byte
+// packets: packet 0 of its kTile links, then packet 1, and so on, so a wave
+// reads each packet of 64 consecutive links as 1 KB in one piece and a whole
+// link of 64 consecutive h from one contiguous stretch of memory:
+//   FP64: one complex element (double2) per packet, NE packets;
+//   FP32: two complex elements (float4) per packet; 18-real storage ends the
+//         tile with the odd element of its links as float2.
 // Every access goes through a LinkRef (slab base, h).
 
 template <int PREC>
@@ -278,69 +281,95 @@ struct LinkRef {
     uint32_t h;   // half-lattice index of the link
 };
 
+// Bytes of one stored link and the address of packet 0 of link h: tile
+// h / kTile, lane h % kTile inside it.
+template <int PREC>
+constexpr size_t link_store_bytes()
+{
+    return size_t(Store<PREC>::NE) * 2 * sizeof(typename Store<PREC>::real);
+}
+
+template <int PREC>
+__device__ __forceinline__ char *tile_of(const LinkRef &r)
+{
+    return r.slab + size_t(r.h / kTile) * (kTile * link_store_bytes<PREC>());
+}
+
+template <int PREC>
+__device__ __forceinline__ char *packet_ptr(const LinkRef &r, int j)
+{
+    return tile_of<PREC>(r) + (size_t(j) * kTile + r.h % kTile) * 16;
+}
+
+// the odd element of FP32 18-real storage, after the tile's four packets
+template <int PREC>
+__device__ __forceinline__ char *tail_ptr(const LinkRef &r)
+{
+    return tile_of<PREC>(r) + size_t(Store<PREC>::NE / 2) * kTile * 16 + size_t(r.h % kTile) * 8;
+}
+
 // complex element e of a link
 template <int PREC>
-__device__ __forceinline__ cx<typename Store<PREC>::real> load_elem(const LinkRef &r, uint32_t Vh, int e)
+__device__ __forceinline__ cx<typename Store<PREC>::real> load_elem(const LinkRef &r, int e)
 {
     using R = typename Store<PREC>::real;
     if constexpr (sizeof(R) == 8) {
-        const double2 v = *reinterpret_cast<const double2 *>(r.slab + (size_t(e) * Vh + r.h) * 16);
+        const double2 v = *reinterpret_cast<const double2 *>(packet_ptr<PREC>(r, e));
         return cx<R>{v.x, v.y};
     } else {
         constexpr int NP = Store<PREC>::NE / 2;
         if (e >= 2 * NP) {
-            const float2 v = *reinterpret_cast<const float2 *>(r.slab + size_t(NP) * Vh * 16 + size_t(r.h) * 8);
+            const float2 v = *reinterpret_cast<const float2 *>(tail_ptr<PREC>(r));
             return cx<R>{v.x, v.y};
         }
-        const float2 v = *reinterpret_cast<const float2 *>(r.slab + (size_t(e >> 1) * Vh + r.h) * 16 + (e & 1) * 8);
+        const float2 v = *reinterpret_cast<const float2 *>(packet_ptr<PREC>(r, e >> 1) + (e & 1) * 8);
         return cx<R>{v.x, v.y};
     }
 }
 
 template <int PREC>
-__device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const LinkRef &r, uint32_t Vh)
+__device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const LinkRef &r)
 {
     using R = typename Store<PREC>::real;
     constexpr int NE = Store<PREC>::NE;
     mat3<R> m;
     if constexpr (sizeof(R) == 8) {
 #pragma unroll
-        for (int e = 0; e < NE; ++e) m.e[e / 3][e % 3] = load_elem<PREC>(r, Vh, e);
+        for (int e = 0; e < NE; ++e) m.e[e / 3][e % 3] = load_elem<PREC>(r, e);
     } else {
         constexpr int NP = NE / 2;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            const float4 v = *reinterpret_cast<const float4 *>(r.slab + (size_t(j) * Vh + r.h) * 16);
+            const float4 v = *reinterpret_cast<const float4 *>(packet_ptr<PREC>(r, j));
             m.e[(2 * j) / 3][(2 * j) % 3] = cx<R>{v.x, v.y};
             m.e[(2 * j + 1) / 3][(2 * j + 1) % 3] = cx<R>{v.z, v.w};
         }
-        if constexpr (NE & 1) m.e[2][2] = load_elem<PREC>(r, Vh, NE - 1);
+        if constexpr (NE & 1) m.e[2][2] = load_elem<PREC>(r, NE - 1);
     }
     if constexpr (NE == 6) third_row(m);
     return m;
 }
 
 template <int PREC>
-__device__ __forceinline__ void store_link(const LinkRef &r, uint32_t Vh, const mat3<double> &m)
+__device__ __forceinline__ void store_link(const LinkRef &r, const mat3<double> &m)
 {
     using R = typename Store<PREC>::real;
     constexpr int NE = Store<PREC>::NE;
     if constexpr (sizeof(R) == 8) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            *reinterpret_cast<double2 *>(r.slab + (size_t(e) * Vh + r.h) * 16) =
+            *reinterpret_cast<double2 *>(packet_ptr<PREC>(r, e)) =
                 make_double2(m.e[e / 3][e % 3].re, m.e[e / 3][e % 3].im);
     } else {
         constexpr int NP = NE / 2;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             const cx<double> a = m.e[(2 * j) / 3][(2 * j) % 3], b = m.e[(2 * j + 1) / 3][(2 * j + 1) % 3];
-            *reinterpret_cast<float4 *>(r.slab + (size_t(j) * Vh + r.h) * 16) =
+            *reinterpret_cast<float4 *>(packet_ptr<PREC>(r, j)) =
                 make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
         }
         if constexpr (NE & 1)
-            *reinterpret_cast<float2 *>(r.slab + size_t(NP) * Vh * 16 + size_t(r.h) * 8) =
-                make_float2(float(m.e[2][2].re), float(m.e[2][2].im));
+            *reinterpret_cast<float2 *>(tail_ptr<PREC>(r)) = make_float2(float(m.e[2][2].re), float(m.e[2][2].im));
     }
 }
 
@@ -381,26 +410,26 @@ __device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
 template <int PREC, bool CLASSES = false>
 __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
                                                   const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
-                                                  const LinkRef &b2, const LinkRef &b3, uint32_t Vh,
+                                                  const LinkRef &b2, const LinkRef &b3,
                                                   typename Store<PREC>::real wf, typename Store<PREC>::real wb,
                                                   cx<typename Store<PREC>::real> *cls = nullptr,
                                                   uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
 {
     using R = typename Store<PREC>::real;
     constexpr bool stream = PREC == kFP64_18;
-    const mat3<R> m3 = load_link<PREC>(f3, Vh);
-    const mat3<R> mb1 = load_link<PREC>(b1, Vh);
+    const mat3<R> m3 = load_link<PREC>(f3);
+    const mat3<R> mb1 = load_link<PREC>(b1);
     // T_ij = wf conj(sum_k F3_jk F2_ki): row k of F2 adds to every T_ij
     mat3<R> T, Tu;
     set_zero(T);
     {
         mat3<R> m2;
-        if constexpr (!stream) m2 = load_link<PREC>(f2, Vh);
+        if constexpr (!stream) m2 = load_link<PREC>(f2);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             cx<R> r2[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(f2, Vh, 3 * k + c) : m2.e[k][c];
+            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(f2, 3 * k + c) : m2.e[k][c];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -416,12 +445,12 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
     mat3<R> S, Su;
     {
         mat3<R> mb2;
-        if constexpr (!stream) mb2 = load_link<PREC>(b2, Vh);
+        if constexpr (!stream) mb2 = load_link<PREC>(b2);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             cx<R> r2[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(b2, Vh, 3 * j + c) : mb2.e[j][c];
+            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(b2, 3 * j + c) : mb2.e[j][c];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 cx<R> s{R(0), R(0)};
@@ -439,16 +468,16 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
         set_zero(Bu);
     }
     if constexpr (!stream) {
-        m1 = load_link<PREC>(f1, Vh);
-        mb3 = load_link<PREC>(b3, Vh);
+        m1 = load_link<PREC>(f1);
+        mb3 = load_link<PREC>(b3);
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         cx<R> r1[3], r3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            r1[c] = stream ? load_elem<PREC>(f1, Vh, 3 * r + c) : m1.e[r][c];
-            r3[c] = stream ? load_elem<PREC>(b3, Vh, 3 * r + c) : mb3.e[r][c];
+            r1[c] = stream ? load_elem<PREC>(f1, 3 * r + c) : m1.e[r][c];
+            r3[c] = stream ? load_elem<PREC>(b3, 3 * r + c) : mb3.e[r][c];
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j)

@@ -105,14 +105,14 @@ __device__ __forceinline__ Step step_bwd(const RepDesc &rep, const Site<D> &x, i
 }
 
 // Reference to link (layer, dir) at the site with number s and parity par:
-// its slab and its half-lattice index s / 2.
+// its slab (Vhp links, whole tiles) and its half-lattice index s / 2.
 template <int D, int PREC>
 __device__ __forceinline__ LinkRef link_ref(void *links, const RepDesc &rep, uint32_t layer, int dir, int par,
                                             uint32_t s)
 {
     constexpr size_t kElemBytes = sizeof(typename Store<PREC>::real) * 2;
     constexpr int NE = Store<PREC>::NE;
-    const size_t slab = size_t((layer * D + uint32_t(dir)) * 2u + uint32_t(par)) * NE * rep.Vh;
+    const size_t slab = size_t((layer * D + uint32_t(dir)) * 2u + uint32_t(par)) * NE * rep.Vhp;
     return LinkRef{reinterpret_cast<char *>(links) + (rep.elem_offset + slab) * kElemBytes, s >> 1};
 }
 

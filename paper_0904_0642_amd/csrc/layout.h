@@ -20,15 +20,21 @@ inline constexpr int bytes_per_elem(int prec) { return (prec == kFP64_18 || prec
 inline constexpr bool is_fp32(int prec) { return prec == kFP32_18 || prec == kFP32_12; }
 inline constexpr int bytes_per_link(int prec) { return elems_per_link(prec) * bytes_per_elem(prec); }
 
+// Links are stored in tiles of kTile consecutive half-lattice sites (one
+// wave); a slab of Vh links takes Vhp = Vh rounded up to whole tiles.
+constexpr uint32_t kTile = 64;
+inline constexpr uint32_t padded_half(uint32_t Vh) { return (Vh + kTile - 1) / kTile * kTile; }
+
 // One lattice ("replica").  A single lattice is a batch of one.  Its links
 // start `elem_offset` complex elements into the batch's link buffer and are
-// laid out as [layer][mu][parity][element][Vh].
+// laid out as [layer][mu][parity][tile][packet][kTile].
 struct RepDesc {
     uint64_t elem_offset;
     int32_t n[kMaxD];        // extents
     uint32_t stride[kMaxD];  // site-number strides: 1, n0, n0 n1, ...
     uint32_t V;              // sites per layer
     uint32_t Vh;             // V / 2
+    uint32_t Vhp;            // Vh rounded up to a multiple of kTile (links per slab in memory)
     uint32_t nlat;           // 1 or 2
     uint32_t glued;          // dlt mask (only with nlat == 2)
     uint32_t lat2test;
@@ -72,6 +78,7 @@ struct UpdateArgs {
     int nhit;                    // KP proposals per subgroup, at most; 0: overrelaxation
     int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
     int order;                   // 0 hardware, 1 XCD-contiguous, 2 XCD slabs, 3 XCD slabs of 3D blocks
+    int reverse;                 // 1: each XCD walks its blocks last to first (alternate slices)
     uint32_t slab;               // orders 2, 3: tiles of the last direction per XCD
     uint32_t cp;                 // orders 2, 3: blocks (order 3: waves) per (x_{D-2}, x_{D-1}) plane
     uint32_t n2;                 // orders 2, 3: extent of direction D-2

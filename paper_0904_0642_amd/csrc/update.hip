@@ -217,7 +217,7 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
                                               link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
                                               link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn),
                                               link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn),
-                                              link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
+                                              link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn),
                                               single ? R(1) : R(tags_f == 0 ? beta0 : beta1),
                                               single ? R(1) : R(tags_b == 0 ? beta0 : beta1), alow, bd, tid,
                                               cf, cb);
@@ -229,7 +229,7 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
                                 link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
                                 link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn),
                                 link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn),
-                                link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn), Vh,
+                                link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn),
                                 single ? R(1) : R(tags_f == 0 ? beta0 : beta1),
                                 single ? R(1) : R(tags_b == 0 ? beta0 : beta1));
     }
@@ -237,7 +237,7 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
 
     // heatbath in the storage precision (FP64 for the draw, see su2_heatbath)
     const LinkRef uptr = link_ref<D, PREC>(a.links, rep, layer, mu, p, x.s);
-    mat3<R> U = load_link<PREC>(uptr, Vh);
+    mat3<R> U = load_link<PREC>(uptr);
     mat3<R> W = mul_nn(U, A);   // A is not needed past this point
     const double tr_old = double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 
@@ -266,7 +266,7 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
             plaq[c] += re_tr_nn(Us, widen<double>(M)) * (1.0 / 3.0);
         }
     }
-    store_link<PREC>(uptr, Vh, Ud);
+    store_link<PREC>(uptr, Ud);
 }
 
 // Sum the per-thread counters over the block and add them to one slot; with
@@ -399,13 +399,26 @@ __device__ __forceinline__ uint32_t link_of_thread_3d(const UpdateArgs &a, uint3
     return (x2 + a.n2 * x3) * a.plane + c * 64u + lane;
 }
 
+// Hardware block b with the walk of every XCD reversed (a.reverse): XCD
+// b mod 8 keeps its blocks but takes them last to first.  Alternate slices
+// walk back and forth, so a slice starts on the links its predecessor read
+// last, while they are still in the last-level cache.
+__device__ __forceinline__ uint32_t walk_block(const UpdateArgs &a)
+{
+    const uint32_t b = blockIdx.x, G = gridDim.x;
+    if (!a.reverse) return b;
+    if ((G & 7u) == 0u) return (b & 7u) | ((G / 8u - 1u - (b >> 3)) << 3);
+    return G - 1u - b;
+}
+
 template <int D, int PREC, int WAVES, int NC = 1>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
+    const uint32_t b = walk_block(a);
     if (a.order == 3)
-        process_block<D, PREC, NC>(a, blockIdx.x, *a.sweep, int64_t(link_of_thread_3d(a, blockIdx.x)));
+        process_block<D, PREC, NC>(a, b, *a.sweep, int64_t(link_of_thread_3d(a, b)));
     else
-        process_block<D, PREC, NC>(a, logical_block(a, blockIdx.x), *a.sweep);
+        process_block<D, PREC, NC>(a, logical_block(a, b), *a.sweep);
 }
 
 // Grid barrier of a persistent launch (all blocks resident: cooperative

@@ -40,6 +40,11 @@ def test_links_bytes():
         assert su3hb.su3hb_links_bytes(p) == 256 * 4 * b
     p = su3hb.make_params([24, 24, 24, 8], nlat=2, dlt_mask=15, precision=su3hb.FP32_18)
     assert su3hb.su3hb_links_bytes(p) == 2 * 24 ** 3 * 8 * 4 * 72
+    # each slab of V/2 links is stored as whole tiles of 64: 6 x 4 has V/2 = 12
+    p = su3hb.make_params([6, 4], precision=su3hb.FP64_18)
+    assert su3hb.su3hb_links_bytes(p) == 2 * 2 * 64 * 144
+    p = su3hb.make_params([6, 6, 4], nlat=2, dlt_mask=7, precision=su3hb.FP32_12)
+    assert su3hb.su3hb_links_bytes(p) == 2 * 3 * 2 * 128 * 48
 
 
 @pytest.mark.parametrize("kw,frag", [

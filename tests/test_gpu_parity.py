@@ -373,11 +373,14 @@ def test_launch_shape_invariance(prec, ext):
     fp32 = prec in (su3hb.FP32_18, su3hb.FP32_12)
     for waves in ((2, 3, 4) if fp32 else (2, 3)):
         for block in (64, 128, 256):
-            for order in (0, 1, 2, 3, 4):
+            for order in (0, 1, 2, 3, 4, 8, 9, 10, 11, 12):
                 g = su3hb.Lattice(ext, seed=8, precision=prec)
                 g.set_launch(block, order, waves)
                 b, o, w = g.get_launch()
-                assert (b, w) == (block, waves) and (o == order or o in (1, 2))
+                # + 8: alternate slices walk backwards; an order that does
+                # not apply falls back to 1 or 2 and keeps the flag
+                assert (b, w) == (block, waves) and o & 8 == order & 8
+                assert o == order or o & 7 in (1, 2)
                 g.sweep(6.1, n_hit=8, n_sweeps=2)
                 links = g.get_links()
                 if ref is None:
@@ -390,6 +393,8 @@ def test_launch_shape_invariance(prec, ext):
             g.set_launch(64, 0, 4)
     with pytest.raises(su3hb.SU3HBError):
         g.set_launch(64, 5, 2)
+    with pytest.raises(su3hb.SU3HBError):
+        g.set_launch(64, 16, 2)
 
 
 def test_graph_replay_equals_direct_launches():
