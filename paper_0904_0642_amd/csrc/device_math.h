@@ -1,5 +1,5 @@
 // device_math.h -- gfx950 device building blocks: complex 3x3 algebra,
-// Philox4x32-10, and the structure-of-arrays link storage.
+// Philox4x32-10, and the tiled link storage.
 #pragma once
 
 #include <hip/hip_runtime.h>
