@@ -399,8 +399,8 @@ __device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
 // loads come in pairs that other threads of the slice read too (F3 of the
 // link at x is B1 of the link at x - mu + nu, F2 of x is B2 of x + 2 nu, F1
 // of x is B3 of x + mu + nu), each pair issued back to back so that the
-// second read of a line finds it still in L2.  FP64-18 streams F2, B2, F1 and
-// B3 row by row to keep registers down; other modes load whole links.
+// second read of a line finds it still in L2.  Every neighbour is loaded as
+// a whole link: with tiled storage that is one contiguous stretch per wave.
 //
 // CLASSES (a measured plane of a two-layer lattice): acc receives exactly the
 // same operations, and the unweighted forward term F1 (F3 F2)^dag and
@@ -416,25 +416,19 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
                                                   uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
 {
     using R = typename Store<PREC>::real;
-    constexpr bool stream = PREC == kFP64_18;
     const mat3<R> m3 = load_link<PREC>(f3);
     const mat3<R> mb1 = load_link<PREC>(b1);
     // T_ij = wf conj(sum_k F3_jk F2_ki): row k of F2 adds to every T_ij
     mat3<R> T, Tu;
     set_zero(T);
     {
-        mat3<R> m2;
-        if constexpr (!stream) m2 = load_link<PREC>(f2);
+        const mat3<R> m2 = load_link<PREC>(f2);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            cx<R> r2[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(f2, 3 * k + c) : m2.e[k][c];
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) cfma_cn(T.e[i][j], m3.e[j][k], cx<R>{r2[i].re, -r2[i].im});
-        }
+                for (int j = 0; j < 3; ++j) cfma_cn(T.e[i][j], m3.e[j][k], cx<R>{m2.e[k][i].re, -m2.e[k][i].im});
         if constexpr (CLASSES) Tu = T;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -444,54 +438,41 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
     // S_ij = wb conj(sum_k B2_jk B1_ki): row j of B2 gives column j of S
     mat3<R> S, Su;
     {
-        mat3<R> mb2;
-        if constexpr (!stream) mb2 = load_link<PREC>(b2);
+        const mat3<R> mb2 = load_link<PREC>(b2);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<R> r2[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) r2[c] = stream ? load_elem<PREC>(b2, 3 * j + c) : mb2.e[j][c];
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 cx<R> s{R(0), R(0)};
 #pragma unroll
-                for (int k = 0; k < 3; ++k) cfma(s, r2[k], mb1.e[k][i]);
+                for (int k = 0; k < 3; ++k) cfma(s, mb2.e[j][k], mb1.e[k][i]);
                 S.e[i][j] = cx<R>{wb * s.re, -wb * s.im};
                 if constexpr (CLASSES) Su.e[i][j] = cx<R>{s.re, -s.im};
             }
-        }
     }
-    // acc += F1 T + S B3, F1 and B3 taken row by row together
-    mat3<R> m1, mb3, Fu, Bu;
+    // acc += F1 T + S B3, row by row
+    const mat3<R> m1 = load_link<PREC>(f1);
+    const mat3<R> mb3 = load_link<PREC>(b3);
+    mat3<R> Fu, Bu;
     if constexpr (CLASSES) {
         set_zero(Fu);
         set_zero(Bu);
     }
-    if constexpr (!stream) {
-        m1 = load_link<PREC>(f1);
-        mb3 = load_link<PREC>(b3);
-    }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        cx<R> r1[3], r3[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            r1[c] = stream ? load_elem<PREC>(f1, 3 * r + c) : m1.e[r][c];
-            r3[c] = stream ? load_elem<PREC>(b3, 3 * r + c) : mb3.e[r][c];
-        }
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                cfma(acc.e[r][j], r1[k], T.e[k][j]);
-                if constexpr (CLASSES) cfma(Fu.e[r][j], r1[k], Tu.e[k][j]);
+                cfma(acc.e[r][j], m1.e[r][k], T.e[k][j]);
+                if constexpr (CLASSES) cfma(Fu.e[r][j], m1.e[r][k], Tu.e[k][j]);
             }
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                cfma(acc.e[i][j], S.e[i][r], r3[j]);
-                if constexpr (CLASSES) cfma(Bu.e[i][j], Su.e[i][r], r3[j]);
+                cfma(acc.e[i][j], S.e[i][r], mb3.e[r][j]);
+                if constexpr (CLASSES) cfma(Bu.e[i][j], Su.e[i][r], mb3.e[r][j]);
             }
     }
     if constexpr (CLASSES) {
