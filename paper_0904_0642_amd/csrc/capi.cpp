@@ -316,7 +316,7 @@ constexpr int kOrderReverse = 8;
 int base_order(const su3hb_lattice *L)
 {
     const int o = L->order & ~kOrderReverse;
-    if (o == 3 && !cube_order_ok(L, L->block)) return slab_order_ok(L, L->block) ? 2 : 1;
+    if ((o == 3 || o == 5) && !cube_order_ok(L, L->block)) return slab_order_ok(L, L->block) ? 2 : 1;
     if ((o == 2 || o == 4) && !slab_order_ok(L, L->block)) return 1;
     return o;
 }
@@ -649,8 +649,8 @@ int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
-    if (order < 0 || (order & ~kOrderReverse) > 4)
-        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 4, optionally + %d", order, kOrderReverse);
+    if (order < 0 || (order & ~kOrderReverse) > 5)
+        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 5, optionally + %d", order, kOrderReverse);
     if (waves != 2 && !(waves == 3 && L->nd == 4) && !(waves == 4 && L->nd == 4 && is_fp32(L->prec)))
         return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4, or 4 for D = 4 with FP32 links", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -890,16 +890,16 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     HIPCHK(hipMemcpyAsync(backup, L->links, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
     const uint64_t sweep0 = L->sweep;
     // candidate shapes: every block size and order, both occupancy targets for
-    // D = 4; orders 2 and 3 only where they apply (otherwise they would repeat
-    // another order), order 3 only with more than one wave per block
+    // D = 4; orders 2 to 5 only where they apply (otherwise they would repeat
+    // another order), orders 3 and 5 only with more than one wave per block
     std::vector<Shape> cands;
     for (int waves : {2, 3, 4}) {
         if (waves >= 3 && L->nd != 4) continue;
         if (waves == 4 && !is_fp32(L->prec)) continue;
         for (int block : {256, 128, 64})
-            for (int order : {0, 1, 2, 3, 4}) {
+            for (int order : {0, 1, 2, 3, 4, 5}) {
                 if ((order == 2 || order == 4) && !slab_order_ok(L, block)) continue;
-                if (order == 3 && (block == 64 || !cube_order_ok(L, block))) continue;
+                if ((order == 3 || order == 5) && (block == 64 || !cube_order_ok(L, block))) continue;
                 cands.push_back(Shape{block, order, waves});
                 cands.push_back(Shape{block, order | kOrderReverse, waves});
             }

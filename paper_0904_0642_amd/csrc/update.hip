@@ -382,7 +382,7 @@ __device__ __forceinline__ uint32_t logical_block(const UpdateArgs &a, uint32_t 
     return b;
 }
 
-// Order 3: a block is tile2 x tile3 waves stacked along x_{D-2} and x_{D-1},
+// Orders 3 and 5: a block is tile2 x tile3 waves stacked along x_{D-2} and x_{D-1},
 // each wave 64 consecutive half-sites of its (x_{D-2}, x_{D-1}) plane, so the
 // neighbours along the two slowest directions are loaded by sibling waves at
 // nearly the same time.  Blocks walk XCD slabs as in order 2.  Returns the
@@ -393,7 +393,9 @@ __device__ __forceinline__ uint32_t link_of_thread_3d(const UpdateArgs &a, uint3
     const uint32_t w2 = w % a.tile2, w3 = w / a.tile2;
     const uint32_t k = b & 7u, e = b >> 3;
     const uint32_t xl = e % a.slab, t = e / a.slab;
-    const uint32_t c = t % a.cp, x2t = t / a.cp;
+    // order 5 walks the x_{D-2} tiles before the chunks of the plane
+    const uint32_t nt2 = a.n2 / a.tile2;
+    const uint32_t c = a.order == 5 ? t / nt2 : t % a.cp, x2t = a.order == 5 ? t % nt2 : t / a.cp;
     const uint32_t x2 = x2t * a.tile2 + w2;
     const uint32_t x3 = (k * a.slab + xl) * a.tile3 + w3;
     return (x2 + a.n2 * x3) * a.plane + c * 64u + lane;
@@ -415,7 +417,7 @@ template <int D, int PREC, int WAVES, int NC = 1>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
     const uint32_t b = walk_block(a);
-    if (a.order == 3)
+    if (a.order == 3 || a.order == 5)
         process_block<D, PREC, NC>(a, b, *a.sweep, int64_t(link_of_thread_3d(a, b)));
     else
         process_block<D, PREC, NC>(a, logical_block(a, b), *a.sweep);
