@@ -184,8 +184,9 @@ int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
  * directions (2 x 2 waves for 256 threads, 1 x 2 for 128; needs planes of a
  * multiple of 64 half-sites); 4 = as 2, walking the block's chunk of the
  * plane slowest and x_{D-2} in the middle; 5 = as 3, walking the x_{D-2}
- * tiles before the chunks of the plane.  Where an order does not apply a
- * lower one that does is used (4 and 2 fall back to 1, 3 and 5 to 2 or 1).
+ * tiles before the chunks of the plane; 6 = as 3, with all waves of a block
+ * along x_{D-2}.  Where an order does not apply a lower one that does is
+ * used (4 and 2 fall back to 1; 3, 5 and 6 to 2 or 1).
  * Adding 8 to an order makes every second slice of a sweep walk each XCD's
  * blocks last to first, so a slice starts on the links the slice before it
  * read last.  waves: minimum waves per SIMD the kernel is compiled for: 2;

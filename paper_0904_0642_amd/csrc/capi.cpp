@@ -288,16 +288,19 @@ bool slab_order_ok(const su3hb_lattice *L, int block)
     return plane % uint32_t(block) == 0;
 }
 
-// Order 3 (3D blocks: tile2 x tile3 waves along x_{D-2}, x_{D-1}) needs one
-// single-layer lattice whose (x_{D-2}, x_{D-1}) planes hold a multiple of 64
-// half-sites, n_{D-2} divisible by tile2 and n_{D-1} by 8 tile3.
-void cube_tiles(int block, uint32_t *t2, uint32_t *t3)
+// Orders 3, 5 and 6 (3D blocks: tile2 x tile3 waves along x_{D-2}, x_{D-1})
+// need one single-layer lattice whose (x_{D-2}, x_{D-1}) planes hold a
+// multiple of 64 half-sites, n_{D-2} divisible by tile2 and n_{D-1} by
+// 8 tile3.  Order 6 puts all waves of a block along x_{D-2}.
+bool is_cube_order(int o) { return o == 3 || o == 5 || o == 6; }
+
+void cube_tiles(int block, int order, uint32_t *t2, uint32_t *t3)
 {
-    *t2 = block == 256 ? 2u : 1u;
+    *t2 = order == 6 ? uint32_t(block) / 64u : block == 256 ? 2u : 1u;
     *t3 = uint32_t(block) / 64u / *t2;
 }
 
-bool cube_order_ok(const su3hb_lattice *L, int block)
+bool cube_order_ok(const su3hb_lattice *L, int block, int order)
 {
     if (L->batch || L->nrep != 1 || L->nd < 3) return false;
     const RepDesc &r = L->reps[0];
@@ -305,7 +308,7 @@ bool cube_order_ok(const su3hb_lattice *L, int block)
     const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
     const uint32_t plane = r.Vh / (nl * n2);
     uint32_t t2, t3;
-    cube_tiles(block, &t2, &t3);
+    cube_tiles(block, order, &t2, &t3);
     return plane % 64u == 0 && n2 % t2 == 0 && nl % (8u * t3) == 0;
 }
 
@@ -316,7 +319,7 @@ constexpr int kOrderReverse = 8;
 int base_order(const su3hb_lattice *L)
 {
     const int o = L->order & ~kOrderReverse;
-    if ((o == 3 || o == 5) && !cube_order_ok(L, L->block)) return slab_order_ok(L, L->block) ? 2 : 1;
+    if (is_cube_order(o) && !cube_order_ok(L, L->block, o)) return slab_order_ok(L, L->block) ? 2 : 1;
     if ((o == 2 || o == 4) && !slab_order_ok(L, L->block)) return 1;
     return o;
 }
@@ -342,7 +345,7 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
             a.slab = nl / 8;
             a.cp = a.plane / uint32_t(L->block);
         } else {
-            cube_tiles(L->block, &a.tile2, &a.tile3);
+            cube_tiles(L->block, a.order, &a.tile2, &a.tile3);
             a.slab = nl / (8u * a.tile3);
             a.cp = a.plane / 64u;
         }
@@ -649,8 +652,8 @@ int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
-    if (order < 0 || (order & ~kOrderReverse) > 5)
-        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 5, optionally + %d", order, kOrderReverse);
+    if (order < 0 || (order & ~kOrderReverse) > 6)
+        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 6, optionally + %d", order, kOrderReverse);
     if (waves != 2 && !(waves == 3 && L->nd == 4) && !(waves == 4 && L->nd == 4 && is_fp32(L->prec)))
         return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4, or 4 for D = 4 with FP32 links", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -890,16 +893,16 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     HIPCHK(hipMemcpyAsync(backup, L->links, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
     const uint64_t sweep0 = L->sweep;
     // candidate shapes: every block size and order, both occupancy targets for
-    // D = 4; orders 2 to 5 only where they apply (otherwise they would repeat
-    // another order), orders 3 and 5 only with more than one wave per block
+    // D = 4; orders 2 to 6 only where they apply (otherwise they would repeat
+    // another order), orders 3, 5 and 6 only with more than one wave per block
     std::vector<Shape> cands;
     for (int waves : {2, 3, 4}) {
         if (waves >= 3 && L->nd != 4) continue;
         if (waves == 4 && !is_fp32(L->prec)) continue;
         for (int block : {256, 128, 64})
-            for (int order : {0, 1, 2, 3, 4, 5}) {
+            for (int order : {0, 1, 2, 3, 4, 5, 6}) {
                 if ((order == 2 || order == 4) && !slab_order_ok(L, block)) continue;
-                if ((order == 3 || order == 5) && (block == 64 || !cube_order_ok(L, block))) continue;
+                if (is_cube_order(order) && (block == 64 || !cube_order_ok(L, block, order))) continue;
                 cands.push_back(Shape{block, order, waves});
                 cands.push_back(Shape{block, order | kOrderReverse, waves});
             }

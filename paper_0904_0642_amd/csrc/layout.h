@@ -77,7 +77,7 @@ struct UpdateArgs {
     int mu;                      // direction being updated
     int nhit;                    // KP proposals per subgroup, at most; 0: overrelaxation
     int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
-    int order;                   // 0 hardware, 1 XCD-contiguous, 2 and 4 XCD slabs, 3 and 5 XCD slabs of 3D blocks
+    int order;                   // 0 hardware, 1 XCD-contiguous, 2 and 4 XCD slabs, 3, 5 and 6 XCD slabs of 3D blocks
     int reverse;                 // 1: each XCD walks its blocks last to first (alternate slices)
     uint32_t slab;               // orders 2, 3: tiles of the last direction per XCD
     uint32_t cp;                 // orders 2, 3: blocks (order 3: waves) per (x_{D-2}, x_{D-1}) plane

@@ -382,7 +382,7 @@ __device__ __forceinline__ uint32_t logical_block(const UpdateArgs &a, uint32_t 
     return b;
 }
 
-// Orders 3 and 5: a block is tile2 x tile3 waves stacked along x_{D-2} and x_{D-1},
+// Orders 3, 5 and 6: a block is tile2 x tile3 waves stacked along x_{D-2} and x_{D-1},
 // each wave 64 consecutive half-sites of its (x_{D-2}, x_{D-1}) plane, so the
 // neighbours along the two slowest directions are loaded by sibling waves at
 // nearly the same time.  Blocks walk XCD slabs as in order 2.  Returns the
@@ -417,7 +417,7 @@ template <int D, int PREC, int WAVES, int NC = 1>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
     const uint32_t b = walk_block(a);
-    if (a.order == 3 || a.order == 5)
+    if (a.order == 3 || a.order == 5 || a.order == 6)
         process_block<D, PREC, NC>(a, b, *a.sweep, int64_t(link_of_thread_3d(a, b)));
     else
         process_block<D, PREC, NC>(a, logical_block(a, b), *a.sweep);

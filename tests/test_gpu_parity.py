@@ -373,7 +373,7 @@ def test_launch_shape_invariance(prec, ext):
     fp32 = prec in (su3hb.FP32_18, su3hb.FP32_12)
     for waves in ((2, 3, 4) if fp32 else (2, 3)):
         for block in (64, 128, 256):
-            for order in (0, 1, 2, 3, 4, 5, 8, 9, 10, 11, 12, 13):
+            for order in (0, 1, 2, 3, 4, 5, 6, 8, 9, 10, 11, 12, 13, 14):
                 g = su3hb.Lattice(ext, seed=8, precision=prec)
                 g.set_launch(block, order, waves)
                 b, o, w = g.get_launch()
@@ -392,7 +392,7 @@ def test_launch_shape_invariance(prec, ext):
         with pytest.raises(su3hb.SU3HBError):
             g.set_launch(64, 0, 4)
     with pytest.raises(su3hb.SU3HBError):
-        g.set_launch(64, 6, 2)
+        g.set_launch(64, 7, 2)
     with pytest.raises(su3hb.SU3HBError):
         g.set_launch(64, 16, 2)
 
