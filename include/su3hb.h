@@ -231,7 +231,7 @@ int su3hb_batch_create(su3hb_batch **out, int nd, const su3hb_replica_desc *reps
 
 /* n_sweeps sweeps of every replica at its own beta.  mode 0: one launch per
  * checkerboard slice covering all replicas; mode 1: one persistent
- * cooperative launch (one 512-thread block per compute unit) that loops over
+ * cooperative launch (256-thread blocks, as many per compute unit as fit) that loops over
  * sweeps and slices with a grid barrier between slices, in launches of at
  * most 65536 sweeps.  Both give bit-identical links.  Mode 1 returns after
  * the work has finished (it synchronises the stream); if a grid barrier

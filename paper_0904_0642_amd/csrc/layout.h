@@ -49,12 +49,13 @@ struct RepDesc {
     uint32_t pers_blocks;
 };
 
-// Persistent batch launches: one block of kPersistentThreads (2 waves per
-// SIMD) per CU, slices separated by a grid barrier on a small array of
-// counters (kBarrierWords words: kBarrierLeaves leaf counters on their own
-// 128-byte lines, the top counter, an abort flag).  Three waves per SIMD
-// would make the FP32 kernels spill and measured slower.
-constexpr int kPersistentThreads = 512;
+// Persistent batch launches: blocks of kPersistentThreads, as many per CU as
+// the kernel's registers allow (2 waves per SIMD for FP64 links, 3 for
+// FP32), slices separated by a grid barrier on a small array of counters
+// (kBarrierWords words: kBarrierLeaves leaf counters on their own 128-byte
+// lines, the top counter, an abort flag).
+constexpr int kPersistentThreads = 256;
+inline constexpr int persistent_waves(int prec) { return (prec == kFP32_18 || prec == kFP32_12) ? 3 : 2; }
 constexpr int kBarrierWords = 2048;
 constexpr uint32_t kBarrierLeaves = 16;
 constexpr uint32_t kBarrierTop = 1024;

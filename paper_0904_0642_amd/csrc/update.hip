@@ -461,8 +461,8 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t gen)
     return s_ok != 0;
 }
 
-// Persistent form for batches: one block per CU stays resident for n_sweeps
-// sweeps, loops over the logical blocks of every slice and meets the others
+// Persistent form for batches: every resident block (as many per CU as fit)
+// stays for n_sweeps sweeps, loops over the logical blocks of every slice and meets the others
 // at a grid barrier between slices (the next slice reads links this one
 // wrote).  Blocks are dealt round-robin to the 8 XCDs, so the blocks of XCD k
 // walk the k-th eighth of the logical blocks together, keeping neighbouring
@@ -470,7 +470,7 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t gen)
 // the local sweep index; the counter itself is advanced once, by the host,
 // after the launch.
 template <int D, int PREC, int THREADS>
-__global__ void __launch_bounds__(THREADS, THREADS / 256) update_persistent_kernel(UpdateArgs a, int n_sweeps)
+__global__ void __launch_bounds__(THREADS, persistent_waves(PREC)) update_persistent_kernel(UpdateArgs a, int n_sweeps)
 {
     const uint32_t sweep0 = *a.sweep;
     const uint32_t G = gridDim.x, T = a.total_blocks;
