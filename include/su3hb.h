@@ -195,7 +195,8 @@ int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
 int su3hb_set_launch(su3hb_lattice *lat, int block, int order, int waves);
 int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *order, int *waves);
 
-/* Time the candidate launch shapes on this lattice for about budget_ms and
+/* Time the candidate launch shapes on this lattice for about budget_ms (two
+ * passes, each shape keeping its faster one) and
  * keep the fastest (cached per precision, D and extents for the process).
  * The links and the sweep counter are restored afterwards.  Synchronises. */
 int su3hb_autotune(su3hb_lattice *lat, int budget_ms);
