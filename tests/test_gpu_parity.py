@@ -144,9 +144,11 @@ def test_lat2test_layers_equal_torus(oracle_mod):
 
 
 @pytest.mark.parametrize("prec", [su3hb.FP32_18, su3hb.FP32_12])
-def test_fp32_storage_one_sweep(oracle_mod, prec):
-    # shared start: the oracle takes the FP32-rounded links the GPU holds
-    g, o = pair(oracle_mod, [8, 8, 8, 4], prec=prec, seed=2)
+@pytest.mark.parametrize("ext", [[8, 8, 8, 4], [6, 4, 2, 10]])
+def test_fp32_storage_one_sweep(oracle_mod, prec, ext):
+    # shared start: the oracle takes the FP32-rounded links the GPU holds;
+    # 6x4x2x10 has 240 links per slab, so its last tile of 64 is partial
+    g, o = pair(oracle_mod, ext, prec=prec, seed=2)
     start = g.get_links()
     o.set_links(start)
     g.sweep(6.0, n_hit=8, n_sweeps=1)
