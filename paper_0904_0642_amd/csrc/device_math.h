@@ -350,6 +350,13 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const Link
     return m;
 }
 
+// A slice writes each link once and reads it back only in later slices, so
+// the stores take the non-temporal policy and leave L2 to the neighbour
+// lines that other threads of the slice read again.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+
 template <int PREC>
 __device__ __forceinline__ void store_link(const LinkRef &r, const mat3<double> &m)
 {
@@ -358,18 +365,19 @@ __device__ __forceinline__ void store_link(const LinkRef &r, const mat3<double> 
     if constexpr (sizeof(R) == 8) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            *reinterpret_cast<double2 *>(packet_ptr<PREC>(r, e)) =
-                make_double2(m.e[e / 3][e % 3].re, m.e[e / 3][e % 3].im);
+            __builtin_nontemporal_store(nt_double2{m.e[e / 3][e % 3].re, m.e[e / 3][e % 3].im},
+                                        reinterpret_cast<nt_double2 *>(packet_ptr<PREC>(r, e)));
     } else {
         constexpr int NP = NE / 2;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             const cx<double> a = m.e[(2 * j) / 3][(2 * j) % 3], b = m.e[(2 * j + 1) / 3][(2 * j + 1) % 3];
-            *reinterpret_cast<float4 *>(packet_ptr<PREC>(r, j)) =
-                make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+            __builtin_nontemporal_store(nt_float4{float(a.re), float(a.im), float(b.re), float(b.im)},
+                                        reinterpret_cast<nt_float4 *>(packet_ptr<PREC>(r, j)));
         }
         if constexpr (NE & 1)
-            *reinterpret_cast<float2 *>(tail_ptr<PREC>(r)) = make_float2(float(m.e[2][2].re), float(m.e[2][2].im));
+            __builtin_nontemporal_store(nt_float2{float(m.e[2][2].re), float(m.e[2][2].im)},
+                                        reinterpret_cast<nt_float2 *>(tail_ptr<PREC>(r)));
     }
 }
 
