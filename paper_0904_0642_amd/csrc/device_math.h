@@ -308,26 +308,40 @@ __device__ __forceinline__ char *tail_ptr(const LinkRef &r)
     return tile_of<PREC>(r) + size_t(Store<PREC>::NE / 2) * kTile * 16 + size_t(r.h % kTile) * 8;
 }
 
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+
+// A packet read with the normal or (NT) the non-temporal cache policy.
+template <typename V, bool NT>
+__device__ __forceinline__ V read_packet(const char *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    else return *reinterpret_cast<const V *>(p);
+}
+
 // complex element e of a link
-template <int PREC>
+template <int PREC, bool NT = false>
 __device__ __forceinline__ cx<typename Store<PREC>::real> load_elem(const LinkRef &r, int e)
 {
     using R = typename Store<PREC>::real;
     if constexpr (sizeof(R) == 8) {
-        const double2 v = *reinterpret_cast<const double2 *>(packet_ptr<PREC>(r, e));
+        const nt_double2 v = read_packet<nt_double2, NT>(packet_ptr<PREC>(r, e));
         return cx<R>{v.x, v.y};
     } else {
         constexpr int NP = Store<PREC>::NE / 2;
         if (e >= 2 * NP) {
-            const float2 v = *reinterpret_cast<const float2 *>(tail_ptr<PREC>(r));
+            const nt_float2 v = read_packet<nt_float2, NT>(tail_ptr<PREC>(r));
             return cx<R>{v.x, v.y};
         }
-        const float2 v = *reinterpret_cast<const float2 *>(packet_ptr<PREC>(r, e >> 1) + (e & 1) * 8);
+        const nt_float2 v = read_packet<nt_float2, NT>(packet_ptr<PREC>(r, e >> 1) + (e & 1) * 8);
         return cx<R>{v.x, v.y};
     }
 }
 
-template <int PREC>
+// A whole link; NT: the non-temporal policy, for a link no other thread of
+// the launch reads.
+template <int PREC, bool NT = false>
 __device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const LinkRef &r)
 {
     using R = typename Store<PREC>::real;
@@ -335,16 +349,16 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const Link
     mat3<R> m;
     if constexpr (sizeof(R) == 8) {
 #pragma unroll
-        for (int e = 0; e < NE; ++e) m.e[e / 3][e % 3] = load_elem<PREC>(r, e);
+        for (int e = 0; e < NE; ++e) m.e[e / 3][e % 3] = load_elem<PREC, NT>(r, e);
     } else {
         constexpr int NP = NE / 2;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            const float4 v = *reinterpret_cast<const float4 *>(packet_ptr<PREC>(r, j));
+            const nt_float4 v = read_packet<nt_float4, NT>(packet_ptr<PREC>(r, j));
             m.e[(2 * j) / 3][(2 * j) % 3] = cx<R>{v.x, v.y};
             m.e[(2 * j + 1) / 3][(2 * j + 1) % 3] = cx<R>{v.z, v.w};
         }
-        if constexpr (NE & 1) m.e[2][2] = load_elem<PREC>(r, NE - 1);
+        if constexpr (NE & 1) m.e[2][2] = load_elem<PREC, NT>(r, NE - 1);
     }
     if constexpr (NE == 6) third_row(m);
     return m;
@@ -353,9 +367,6 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const Link
 // A slice writes each link once and reads it back only in later slices, so
 // the stores take the non-temporal policy and leave L2 to the neighbour
 // lines that other threads of the slice read again.
-typedef double nt_double2 __attribute__((ext_vector_type(2)));
-typedef float nt_float4 __attribute__((ext_vector_type(4)));
-typedef float nt_float2 __attribute__((ext_vector_type(2)));
 
 template <int PREC>
 __device__ __forceinline__ void store_link(const LinkRef &r, const mat3<double> &m)

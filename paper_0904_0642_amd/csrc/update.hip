@@ -237,7 +237,7 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
 
     // heatbath in the storage precision (FP64 for the draw, see su2_heatbath)
     const LinkRef uptr = link_ref<D, PREC>(a.links, rep, layer, mu, p, x.s);
-    mat3<R> U = load_link<PREC>(uptr);
+    mat3<R> U = load_link<PREC, true>(uptr);   // no other thread of the slice reads U
     mat3<R> W = mul_nn(U, A);   // A is not needed past this point
     const double tr_old = double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 
