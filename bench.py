@@ -205,32 +205,57 @@ def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int =
     return res
 
 
-def dlt_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int):
+def dlt_leg(n_hit: int, autotune_ms: int, nsweeps: int = 500, ntherm: int = 100):
     """Double-layered torus: two 24^3 x 8 layers glued in all directions,
-    beta0 = beta1 = 5.69, FP32 links, plaquettes every sweep."""
+    beta0 = beta1 = 5.69, hot start from seed 1, nsweeps sweeps with the
+    plaquettes measured after every sweep, in FP64-18, FP32-18 and FP32-12
+    storage from the same seed.  Each observable of the FP32 chains (total,
+    spacelike, timelike, per layer, the beta-weighted action) is compared with
+    the FP64-18 chain in units of the combined jackknife error (bins of at
+    least 4 tau_int) over the sweeps after ntherm; the FP64-18 path itself is
+    compared with the FP64 oracle in the test suite."""
     import torch
 
     import paper_0904_0642_amd as su3hb
+    from paper_0904_0642_amd.analysis import jackknife_mean, tau_int
+
+    def nbins(x):
+        # bins of at least 4 tau_int sweeps, 8 to 20 of them
+        return int(max(8, min(20, len(x) // max(1, int(np.ceil(4 * tau_int(x)[0]))))))
 
     ext, beta = (24, 24, 24, 8), 5.69
-    lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0xF, precision=su3hb.FP32_18, seed=1)
-    if autotune_ms > 0:
-        lat.autotune(autotune_ms)
-    if warmup > 0:
-        lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    timing, series = lat.sweep_timed(beta, n_hit=n_hit, n_sweeps=steps, measure=True)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
     links = 2 * int(np.prod(ext)) * 4
-    res = {"value": round(steps * links / secs, 1), "unit": "link updates/s", "links_per_sweep": links,
-           "update_kernel_ms": round(timing[0] / max(timing[1], 1), 5),
-           "plaquette_kernel_ms": round(timing[2] / max(timing[3], 1), 5),
-           "plaquette_first_last": [float(series[0, 0]), float(series[-1, 0])],
-           "layers_last": [float(series[-1, 3]), float(series[-1, 4])]}
-    lat.close()
-    torch.cuda.empty_cache()
+    names = ("total", "spacelike", "timelike", "layer0", "layer1", "action")
+    res = {"lattice": "2 x 24^3 x 8, all directions glued", "beta": beta, "sweeps": nsweeps,
+           "thermalisation_sweeps": ntherm, "links_per_sweep": links, "unit": "link updates/s"}
+    ser = {}
+    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
+        lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0xF, precision=prec, seed=1)
+        if autotune_ms > 0:
+            lat.autotune(autotune_ms)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=nsweeps)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ser[prec] = s[ntherm:]
+        res[PREC_NAME[prec]] = {"value": round(nsweeps * links / secs, 1),
+                                "launch": dict(zip(("block", "order", "waves"), lat.get_launch()))}
+        lat.close()
+        torch.cuda.empty_cache()
+    nb = {k: min(nbins(ser[p][:, c]) for p in ser) for c, k in enumerate(names)}
+    ref = {k: jackknife_mean(ser[su3hb.FP64_18][:, c], nb[k]) for c, k in enumerate(names)}
+    res["fp64-18"]["observables"] = {k: [round(m, 9), float(f"{e:.3g}")] for k, (m, e) in ref.items()}
+    res["jackknife_bins"] = nb
+    for prec in (su3hb.FP32_18, su3hb.FP32_12):
+        obs, dev = {}, {}
+        for c, k in enumerate(names):
+            m, e = jackknife_mean(ser[prec][:, c], nb[k])
+            obs[k] = [round(m, 9), float(f"{e:.3g}")]
+            dev[k] = round((m - ref[k][0]) / np.hypot(e, ref[k][1]), 2)
+        res[PREC_NAME[prec]]["observables"] = obs
+        res[PREC_NAME[prec]]["delta_vs_fp64_in_sigma"] = dev
+        res[PREC_NAME[prec]]["rate_ratio_vs_fp64"] = round(res[PREC_NAME[prec]]["value"] / res["fp64-18"]["value"], 3)
     return res
 
 
@@ -274,16 +299,15 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 2000):
     return res
 
 
-def cpu_baseline(name: str, n_hit: int, min_secs: float = 10.0, max_sweeps: int = 6):
-    """The FP64 oracle on a bounded sample of the same workload: checkerboard
-    slices of the hot-started lattice in sweep order (parity 0, 1; directions
-    0..D-1), with OpenMP over the sites of a slice on the host cores, until
-    min_secs have passed or max_sweeps sweeps are done."""
+def oracle_rate(name: str, n_hit: int, threads: int, min_secs: float, max_sweeps: int):
+    """Link updates per second of the FP64 oracle on checkerboard slices of
+    the hot-started lattice in sweep order (parity 0, 1; directions
+    0..D-1), with OpenMP over the sites of a slice, until min_secs have
+    passed or max_sweeps sweeps are done (at least one slice)."""
     import oracle
 
     ext, prec, beta = WORKLOADS[name]
     D = len(ext)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = oracle.Lattice(list(ext), seed=1, threads=threads)
     o.hot_start()
     V = int(np.prod(ext))
@@ -296,10 +320,24 @@ def cpu_baseline(name: str, n_hit: int, min_secs: float = 10.0, max_sweeps: int 
             break
     secs = time.perf_counter() - t0
     n = slices * (V // 2)
-    return {"value": n / secs, "unit": "link updates/s", "cores": threads, "kind": "oracle",
+    del o
+    return n / secs, slices, n, secs
+
+
+def cpu_baseline(name: str, n_hit: int, min_secs: float = 10.0, max_sweeps: int = 6):
+    """The FP64 oracle on a bounded sample of the same workload, on all host
+    threads the run may use and on one thread."""
+    ext, prec, beta = WORKLOADS[name]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rate, slices, n, secs = oracle_rate(name, n_hit, threads, min_secs, max_sweeps)
+    rate1, slices1, n1, secs1 = oracle_rate(name, n_hit, 1, min_secs / 2, max_sweeps)
+    return {"value": rate, "unit": "link updates/s", "cores": threads, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
             "sample": f"{slices} checkerboard slices in sweep order ({n} link updates) of the hot-started "
                       f"{'x'.join(map(str, ext))} lattice at beta={beta}, n_hit={n_hit}, FP64 C oracle, "
-                      f"OpenMP {threads} threads, {secs:.2f} s"}
+                      f"OpenMP {threads} threads, {secs:.2f} s",
+            "single_thread": {"value": rate1, "unit": "link updates/s", "cores": 1,
+                              "sample": f"{slices1} slices ({n1} link updates), 1 thread, {secs1:.2f} s"}}
 
 
 def main():
@@ -383,7 +421,7 @@ def main():
         }
     if not args.no_extra_legs:
         line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
-        line["dlt_2x24^3x8_fp32"] = dlt_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
+        line["dlt_2x24^3x8"] = dlt_leg(args.n_hit, args.autotune_ms)
         line["precision_study"] = precision_study(args.n_hit)
         line["overrelaxation_" + args.workload] = overrelax_leg(args.workload, args.steps, args.warmup,
                                                                 args.autotune_ms)

@@ -83,6 +83,9 @@ def lib():
         L.or_update_link.argtypes = [C.c_void_p, C.c_int, C.c_long, C.c_int, C.c_double, C.c_double,
                                      C.c_int]
         L.or_update_link.restype = C.c_double
+        L.or_link_margin.argtypes = [C.c_void_p, C.c_int, C.c_long, C.c_int, C.c_double, C.c_double,
+                                     C.c_int]
+        L.or_link_margin.restype = C.c_double
         L.or_update_slice.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                                       C.POINTER(C.c_long)]
         L.or_update_slice.restype = C.c_double
@@ -239,6 +242,12 @@ class Lattice:
         beta1 = beta0 if beta1 is None else beta1
         return lib().or_update_link(self._h, int(layer), int(s), int(mu), float(beta0), float(beta1),
                                     int(nhit))
+
+    def link_margin(self, layer, s, mu, beta0, beta1=None, nhit=8) -> float:
+        """Smallest |R4^2 - (1 - delta/2)| over the proposals the update of
+        this link would evaluate now (the lattice is not changed)."""
+        beta1 = beta0 if beta1 is None else beta1
+        return lib().or_link_margin(self._h, int(layer), int(s), int(mu), float(beta0), float(beta1), int(nhit))
 
     def update_slice(self, p, mu, beta0, beta1=None, nhit=8, order=None) -> float:
         beta1 = beta0 if beta1 is None else beta1

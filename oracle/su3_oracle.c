@@ -259,7 +259,7 @@ static void staple(const olat *L, int layer, long s, int mu, double beta0, doubl
  * from the Gamma(3/2) density ~ sqrt(delta) exp(-alpha delta) and accepted
  * with probability sqrt(1 - delta/2).  Returns the accepted hit or -1. */
 static int kp_multihit(double alpha, int nhit, const uint32_t key[2], uint32_t lid,
-                       uint32_t sweep, int sub, double *x0, uint64_t *attempts)
+                       uint32_t sweep, int sub, double *x0, uint64_t *attempts, double *margin)
 {
     for (int hit = 0; hit < nhit; ++hit) {
         double r[4];
@@ -267,6 +267,10 @@ static int kp_multihit(double alpha, int nhit, const uint32_t key[2], uint32_t l
         ++*attempts;
         double c = cos(OR_TWO_PI * r[1]);
         double delta = -(log(r[0]) + c * c * log(r[2])) / alpha;
+        /* distance of this proposal from the accept/reject threshold (only
+         * observed, for the rounding study of Sec. 3) */
+        if (margin && fabs(r[3] * r[3] - (1.0 - 0.5 * delta)) < *margin)
+            *margin = fabs(r[3] * r[3] - (1.0 - 0.5 * delta));
         if (r[3] * r[3] <= 1.0 - 0.5 * delta) {
             *x0 = 1.0 - delta;
             return hit;
@@ -279,7 +283,7 @@ int or_kp_draw(double alpha, int nhit, uint64_t seed, uint32_t lid, uint32_t swe
                double *x0, uint64_t *attempts)
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    return kp_multihit(alpha, nhit, key, lid, sweep, sub, x0, attempts);
+    return kp_multihit(alpha, nhit, key, lid, sweep, sub, x0, attempts, NULL);
 }
 
 static const int SUB_I[3] = {0, 0, 1};
@@ -288,7 +292,7 @@ static const int SUB_J[3] = {1, 2, 2};
 /* One CM update of the link matrix u for the staple a: the three SU(2)
  * subgroups in turn, then reunitarisation.  Counts proposals and accepts. */
 static void cm_update(su3 *u, const su3 *a, int nhit, const uint32_t key[2], uint32_t lid,
-                      uint32_t sweep, uint64_t attempts[3], uint64_t accepts[3])
+                      uint32_t sweep, uint64_t attempts[3], uint64_t accepts[3], double *margin)
 {
     for (int sub = 0; sub < 3; ++sub) {
         int i = SUB_I[sub], j = SUB_J[sub];
@@ -303,7 +307,7 @@ static void cm_update(su3 *u, const su3 *a, int nhit, const uint32_t key[2], uin
         double alpha = 2.0 * k / 3.0;
 
         double x0;
-        int hit = kp_multihit(alpha, nhit, key, lid, sweep, sub, &x0, &attempts[sub]);
+        int hit = kp_multihit(alpha, nhit, key, lid, sweep, sub, &x0, &attempts[sub], margin);
         if (hit < 0) continue;                          /* keep the link */
         ++accepts[sub];
 
@@ -377,7 +381,7 @@ void or_cm_update_matrix(double *u18, const double *a18, int nhit, uint64_t seed
                          uint32_t sweep, uint64_t attempts[3], uint64_t accepts[3])
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    cm_update((su3 *)u18, (const su3 *)a18, nhit, key, lid, sweep, attempts, accepts);
+    cm_update((su3 *)u18, (const su3 *)a18, nhit, key, lid, sweep, attempts, accepts, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -522,7 +526,7 @@ static double update_link(olat *L, int layer, long s, int mu, double beta0, doub
     if (nhit == 0)
         cm_reflect(U, &A, attempts, accepts);   /* overrelaxation, reading R-OR */
     else
-        cm_update(U, &A, nhit, L->key, link_id(L, layer, s, mu), L->sweep, attempts, accepts);
+        cm_update(U, &A, nhit, L->key, link_id(L, layer, s, mu), L->sweep, attempts, accepts, NULL);
     su3 d;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) d.m[i][j] = U->m[i][j] - old.m[i][j];
@@ -534,6 +538,23 @@ double or_update_link(void *h, int layer, long s, int mu, double beta0, double b
 {
     uint64_t at[3] = {0, 0, 0}, ac[3] = {0, 0, 0};
     return update_link((olat *)h, layer, s, mu, beta0, beta1, nhit, at, ac);
+}
+
+/* Smallest |R4^2 - (1 - delta/2)| over the Kennedy-Pendleton proposals that
+ * the update of link (layer, s, mu) evaluates in the current configuration:
+ * how close its accept/reject decisions come to the threshold (Sec. 3 notes
+ * that rounding differences between platforms eventually flip such
+ * decisions).  The lattice is left unchanged. */
+double or_link_margin(void *h, int layer, long s, int mu, double beta0, double beta1, int nhit)
+{
+    olat *L = (olat *)h;
+    su3 A;
+    staple(L, layer, s, mu, beta0, beta1, &A);
+    su3 u = *link_at(L, layer, s, mu);
+    uint64_t at[3] = {0, 0, 0}, ac[3] = {0, 0, 0};
+    double margin = INFINITY;
+    cm_update(&u, &A, nhit, L->key, link_id(L, layer, s, mu), L->sweep, at, ac, &margin);
+    return margin;
 }
 
 /* One checkerboard slice: every link U_mu(x) with parity(x) = p, in every

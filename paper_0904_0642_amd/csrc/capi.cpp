@@ -423,6 +423,17 @@ int enqueue_sweep(su3hb_lattice *L, hipStream_t st, double b0, double b1, int nh
         a.meas_classes = meas_classes(L);
     }
     const dim3 grid = update_grid(L), block(L->block);
+    {
+        // the largest LDS request of the sweep (a measured parity-1 slice)
+        // must fit one block's share of the compute unit
+        UpdateArgs m = a;
+        m.parity = 1;
+        size_t need = 0, limit = 0;
+        HIPCHK(update_lds(L->nd, L->prec, L->waves, block, m, &need, &limit));
+        if (limit == 0 || need > limit)
+            return fail(SU3HB_EUNSUPPORTED, "update launch needs %zu bytes of LDS per block, the device allows %zu",
+                        need, limit);
+    }
     for (int p = 0; p < 2; ++p)
         for (int mu = 0; mu < L->nd; ++mu) {
             a.parity = p;
@@ -1021,16 +1032,16 @@ int su3hb_batch_create(su3hb_batch **out, int nd, const su3hb_replica_desc *reps
     *out = nullptr;
     if (!reps || n < 1) return fail(SU3HB_EINVAL, "need at least one replica");
     if (precision < 0 || precision > 3) return fail(SU3HB_EINVAL, "unknown precision %d", precision);
-    double links = 0;
     for (int r = 0; r < n; ++r) {
         uint64_t V;
         int rc = check_extents(nd, reps[r].extents, &V);
         if (rc) return fail(rc, "replica %d: %s", r, g_err.c_str());
         if (!std::isfinite(reps[r].beta)) return fail(SU3HB_EINVAL, "replica %d: beta not finite", r);
         if (reps[r].start < 0 || reps[r].start > 2) return fail(SU3HB_EINVAL, "replica %d: bad start", r);
-        links += double(V) * nd;
+        // each replica numbers its links from 0 in the Philox counter (32 bits)
+        if (V * uint64_t(nd) > uint64_t(0xFFFFFFFFu))
+            return fail(SU3HB_EINVAL, "replica %d: more than 2^32 links: the Philox counter holds a 32-bit link id", r);
     }
-    (void)links;
     su3hb_lattice *L = new su3hb_lattice;
     L->nd = nd;
     L->prec = precision;

@@ -230,12 +230,138 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// sin(pi x), cos(pi x) in the precision of x
-__device__ __forceinline__ void sincos_pi(double x, double *s, double *c) { sincospi(x, s, c); }
-__device__ __forceinline__ void sincos_pi(float x, float *s, float *c) { sincospif(x, s, c); }
-
 // 32-bit word -> uniform double (r + 1) / 2^32 in (0, 1]
-__device__ __forceinline__ double u01(uint32_t r) { return (double(r) + 1.0) * 0x1p-32; }
+__host__ __device__ __forceinline__ double u01(uint32_t r) { return (double(r) + 1.0) * 0x1p-32; }
+
+// ---------------------------------------------------------------------------
+// Elementary functions of a uniform u in (0, 1] (a Philox word (r+1)/2^32,
+// so u has at most 32 significant bits), written for this range only: a
+// few FP64 operations instead of the general library routines, which handle
+// every argument.  Each is its Taylor series after an exact reduction.
+
+// ln u to about one ulp: u = 2^e m with m in [sqrt(1/2), sqrt(2)) (exact),
+// ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 3 - 2 sqrt(2) (m - 1 is
+// exact), atanh s = s + s^3/3 + ... + s^19/19 (the first omitted term is
+// below 2^-58 relative), and ln u = e ln2_hi + (ln m + e ln2_lo), where ln2_hi
+// is ln 2 with its last 11 mantissa bits cleared, so e ln2_hi is exact.
+__host__ __device__ __forceinline__ double log_unit(double u)
+{
+    int e = 0;
+    double m = frexp(u, &e);  // u = m 2^e, m in [1/2, 1)
+    if (m < 0x1.6a09e667f3bcdp-1) {  // below sqrt(1/2): m in [1, sqrt(2))
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 19;
+    p = fma(p, z, 1.0 / 17);
+    p = fma(p, z, 1.0 / 15);
+    p = fma(p, z, 1.0 / 13);
+    p = fma(p, z, 1.0 / 11);
+    p = fma(p, z, 1.0 / 9);
+    p = fma(p, z, 1.0 / 7);
+    p = fma(p, z, 1.0 / 5);
+    p = fma(p, z, 1.0 / 3);
+    const double t = 2.0 * s;                    // exact
+    const double lm = fma(t * z, p, t);          // ln m = 2s + 2s z p(z)
+    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
+    const double de = double(e);
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+}
+
+// cos^2(2 pi u): with t = 4u = k + f (k = nearest integer, |f| <= 1/2, both
+// exact), 2 pi u = (pi/2)(k + f), so cos^2(2 pi u) = (1 + cos(pi f))/2 for
+// even k and (1 - cos(pi f))/2 for odd k.  cos(pi f) = sum_n c_n f^(2n),
+// c_n = (-1)^n pi^(2n)/(2n)!, through n = 11 (the next term is below 1e-19).
+__host__ __device__ __forceinline__ double cos2_turn(double u)
+{
+    const double t = 4.0 * u;
+    const double k = rint(t);
+    const double f = t - k;
+    const double w = f * f;
+    double c = -0x1.52ae4120fde27p-34;
+    c = fma(c, w, 0x1.ef6e308d6d1c4p-29);
+    c = fma(c, w, -0x1.2a0c591af8314p-23);
+    c = fma(c, w, 0x1.20c62c2f2d7f5p-18);
+    c = fma(c, w, -0x1.b6e24f44b128fp-14);
+    c = fma(c, w, 0x1.f9d38a3763cc3p-10);
+    c = fma(c, w, -0x1.a6d1f2a204a8cp-6);
+    c = fma(c, w, 0x1.e1f506891babbp-3);
+    c = fma(c, w, -0x1.55d3c7e3cbffap+0);
+    c = fma(c, w, 0x1.03c1f081b5ac4p+2);
+    c = fma(c, w, -0x1.3bd3cc9be45dep+2);
+    c = fma(c, w, 1.0);  // cos(pi f)
+    const bool odd = (int64_t(k) & 1) != 0;
+    return 0.5 + (odd ? -0.5 : 0.5) * c;
+}
+
+// sin(2 pi u) and cos(2 pi u) in T (float or double): with t = 4u = k + f as
+// above, 2 pi u = (pi/2) k + x, x = (pi/2) f in [-pi/4, pi/4]; sin x and
+// cos x from their Taylor series in f (float: through f^9 and f^10, double:
+// through f^17 and f^18, each next term below the precision's half ulp),
+// then rotated by the quarter turns k mod 4.
+template <typename T>
+__host__ __device__ __forceinline__ void sincos_turn(double u, T *sn, T *cs);
+
+template <>
+__host__ __device__ __forceinline__ void sincos_turn<float>(double u, float *sn, float *cs)
+{
+    const double t = 4.0 * u;
+    const double k = rint(t);
+    const float f = float(t - k);
+    const float w = f * f;
+    // sin((pi/2) f) / f = sum_n (-1)^n (pi/2)^(2n+1) w^n / (2n+1)!,
+    // cos((pi/2) f) = sum_n (-1)^n (pi/2)^(2n) w^n / (2n)!
+    float sp = 0x1.507834p-13f;
+    sp = fmaf(sp, w, -0x1.32d2ccp-8f);
+    sp = fmaf(sp, w, 0x1.466bc6p-4f);
+    sp = fmaf(sp, w, -0x1.4abbcep-1f);
+    sp = fmaf(sp, w, 0x1.921fb6p+0f);
+    float cp = -0x1.a6d1f2p-16f;
+    cp = fmaf(cp, w, 0x1.e1f506p-11f);
+    cp = fmaf(cp, w, -0x1.55d3c8p-6f);
+    cp = fmaf(cp, w, 0x1.03c1f0p-2f);
+    cp = fmaf(cp, w, -0x1.3bd3ccp+0f);
+    cp = fmaf(cp, w, 1.0f);
+    const float S = sp * f, C = cp;
+    const int q = int(int64_t(k) & 3);
+    *sn = q == 0 ? S : q == 1 ? C : q == 2 ? -S : -C;
+    *cs = q == 0 ? C : q == 1 ? -S : q == 2 ? -C : S;
+}
+
+template <>
+__host__ __device__ __forceinline__ void sincos_turn<double>(double u, double *sn, double *cs)
+{
+    const double t = 4.0 * u;
+    const double k = rint(t);
+    const double f = t - k;
+    const double w = f * f;
+    double sp = -0x1.8a404211f9547p-45;
+    sp = fma(sp, w, 0x1.aaec32af93359p-38);
+    sp = fma(sp, w, -0x1.6fadb9f155744p-31);
+    sp = fma(sp, w, 0x1.e8f434d018d63p-25);
+    sp = fma(sp, w, -0x1.e3074fde8871fp-19);
+    sp = fma(sp, w, 0x1.50783487ee782p-13);
+    sp = fma(sp, w, -0x1.32d2cce62bd86p-8);
+    sp = fma(sp, w, 0x1.466bc6775aae2p-4);
+    sp = fma(sp, w, -0x1.4abbce625be53p-1);
+    sp = fma(sp, w, 0x1.921fb54442d18p+0);
+    double cp = -0x1.2a0c591af8314p-41;
+    cp = fma(cp, w, 0x1.20c62c2f2d7f5p-34);
+    cp = fma(cp, w, -0x1.b6e24f44b128fp-28);
+    cp = fma(cp, w, 0x1.f9d38a3763cc3p-22);
+    cp = fma(cp, w, -0x1.a6d1f2a204a8cp-16);
+    cp = fma(cp, w, 0x1.e1f506891babbp-11);
+    cp = fma(cp, w, -0x1.55d3c7e3cbffap-6);
+    cp = fma(cp, w, 0x1.03c1f081b5ac4p-2);
+    cp = fma(cp, w, -0x1.3bd3cc9be45dep+0);
+    cp = fma(cp, w, 1.0);
+    const double S = sp * f, C = cp;
+    const int q = int(int64_t(k) & 3);
+    *sn = q == 0 ? S : q == 1 ? C : q == 2 ? -S : -C;
+    *cs = q == 0 ? C : q == 1 ? -S : q == 2 ? -C : S;
+}
 
 constexpr uint32_t kTagUpdate = 0;
 constexpr uint32_t kTagStart = 1;
@@ -426,6 +552,109 @@ __device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
 // backward term (B2 B1)^dag B3 are also added to the measurement classes cf
 // and cb, held in LDS as cls[(c * 9 + e) * stride + t] (slot t of class c,
 // element e).
+// Rows 0 and 1 of a link as stored by 12-real storage (row 2 left unset).
+template <int PREC>
+__device__ __forceinline__ mat3<typename Store<PREC>::real> load_rows01(const LinkRef &r)
+{
+    using R = typename Store<PREC>::real;
+    static_assert(Store<PREC>::NE == 6 && sizeof(R) == 4, "rows 0 and 1 of FP32 12-real storage");
+    mat3<R> m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const nt_float4 v = read_packet<nt_float4, false>(packet_ptr<PREC>(r, j));
+        m.e[(2 * j) / 3][(2 * j) % 3] = cx<R>{v.x, v.y};
+        m.e[(2 * j + 1) / 3][(2 * j + 1) % 3] = cx<R>{v.z, v.w};
+    }
+    return m;
+}
+
+// Both staples of one plane for FP32 12-real storage.  Every product of
+// SU(3) matrices is in SU(3), so only its rows 0 and 1 are multiplied out
+// and row 2 is conj(row0 x row1); then F3, F1 and B2 are needed only as
+// the two rows storage holds:
+//   M = F3 F2 (rows 0, 1 from F3's stored rows), Q = F1 M^dag (rows 0, 1
+//   from F1's stored rows): forward staple F1 (F3 F2)^dag = Q;
+//   N = B2 B1 (rows 0, 1 from B2's stored rows), R = N^dag B3: backward
+//   staple (B2 B1)^dag B3 = R;
+// acc += wf Q + wb R.  The loads keep the partner-pair order of the general
+// form below.  CLASSES as there, with Q and R as the unweighted terms.
+template <int PREC, bool CLASSES>
+__device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
+                                                     const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
+                                                     const LinkRef &b2, const LinkRef &b3,
+                                                     typename Store<PREC>::real wf, typename Store<PREC>::real wb,
+                                                     cx<typename Store<PREC>::real> *cls, uint32_t stride,
+                                                     uint32_t t, int cf, int cb)
+{
+    using R = typename Store<PREC>::real;
+    const mat3<R> m3 = load_rows01<PREC>(f3);
+    const mat3<R> mb1 = load_link<PREC>(b1);
+    mat3<R> M;
+    {
+        const mat3<R> m2 = load_link<PREC>(f2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                cx<R> s{R(0), R(0)};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cfma(s, m3.e[j][k], m2.e[k][i]);
+                M.e[j][i] = s;
+            }
+        third_row(M);
+    }
+    mat3<R> N;
+    {
+        const mat3<R> mb2 = load_rows01<PREC>(b2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                cx<R> s{R(0), R(0)};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cfma(s, mb2.e[j][k], mb1.e[k][i]);
+                N.e[j][i] = s;
+            }
+        third_row(N);
+    }
+    const mat3<R> m1 = load_rows01<PREC>(f1);
+    const mat3<R> mb3 = load_link<PREC>(b3);
+    mat3<R> Q, Rb;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<R> q{R(0), R(0)}, b{R(0), R(0)};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cfma_nc(q, m1.e[r][k], M.e[j][k]);   // (F1 M^dag)_rj
+                cfma_cn(b, N.e[k][r], mb3.e[k][j]);  // (N^dag B3)_rj
+            }
+            Q.e[r][j] = q;
+            Rb.e[r][j] = b;
+        }
+    third_row(Q);
+    third_row(Rb);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            acc.e[i][j].re = fma(wf, Q.e[i][j].re, fma(wb, Rb.e[i][j].re, acc.e[i][j].re));
+            acc.e[i][j].im = fma(wf, Q.e[i][j].im, fma(wb, Rb.e[i][j].im, acc.e[i][j].im));
+        }
+    if constexpr (CLASSES) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            cx<R> &fe = cls[(cf * 9 + e) * stride + t];
+            fe.re += Q.e[e / 3][e % 3].re;
+            fe.im += Q.e[e / 3][e % 3].im;
+            cx<R> &be = cls[(cb * 9 + e) * stride + t];
+            be.re += Rb.e[e / 3][e % 3].re;
+            be.im += Rb.e[e / 3][e % 3].im;
+        }
+    }
+}
+
 template <int PREC, bool CLASSES = false>
 __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
                                                   const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
@@ -435,6 +664,10 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
                                                   uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
 {
     using R = typename Store<PREC>::real;
+    if constexpr (Store<PREC>::NE == 6 && sizeof(R) == 4) {
+        acc_plane_staples_12<PREC, CLASSES>(acc, f1, f2, f3, b1, b2, b3, wf, wb, cls, stride, t, cf, cb);
+        return;
+    }
     const mat3<R> m3 = load_link<PREC>(f3);
     const mat3<R> mb1 = load_link<PREC>(b1);
     // T_ij = wf conj(sum_k F3_jk F2_ki): row k of F2 adds to every T_ij

@@ -12,6 +12,10 @@ namespace su3hb {
 hipError_t launch_update(int D, int prec, int waves, dim3 grid, dim3 block, hipStream_t st,
                          const UpdateArgs &a);
 
+// LDS one block of such a launch needs (static + dynamic) and the device's
+// per-block limit; the caller refuses launches that would not fit
+hipError_t update_lds(int D, int prec, int waves, dim3 block, const UpdateArgs &a, size_t *need, size_t *limit);
+
 // persistent cooperative batch sweep: n_sweeps x 2D slices with a grid barrier
 // persistent batch sweeps: kPersistentThreads per block, a.barrier zeroed beforehand
 hipError_t launch_update_persistent(int D, int prec, int blocks, hipStream_t st, const UpdateArgs &a, int n_sweeps);

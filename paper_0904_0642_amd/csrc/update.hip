@@ -66,8 +66,8 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
         const uint4 r = philox4x32_10(
             make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1), kTagUpdate), k0, k1);
         ++attempts;
-        const double c = cospi(2.0 * u01(r.y));  // cos(2 pi u)
-        delta = -(log(u01(r.x)) + c * c * log(u01(r.z))) * inv_alpha;
+        const double c2 = cos2_turn(u01(r.y));  // cos^2(2 pi u)
+        delta = -(log_unit(u01(r.x)) + c2 * log_unit(u01(r.z))) * inv_alpha;
         const double r4 = u01(r.w);
         if (r4 * r4 <= 1.0 - 0.5 * delta) {
             ok = true;
@@ -86,7 +86,7 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
     const H cth = H(2.0 * u01(q.x) - 1.0);
     const H sth = sqrt(max(H(0), H(1) - cth * cth));
     H sph, cph;
-    sincos_pi(H(2.0 * u01(q.y)), &sph, &cph);  // phi = 2 pi u
+    sincos_turn<H>(u01(q.y), &sph, &cph);  // phi = 2 pi u
     const H x1 = rad * sth * cph, x2 = rad * sth * sph, x3 = rad * cth;
 
     // r = X V^dag, X = [[x0 + i x3, x2 + i x1], [-x2 + i x1, x0 - i x3]],
@@ -510,32 +510,59 @@ static size_t update_lds_bytes(dim3 block, const UpdateArgs &a)
     return (a.meas != nullptr && a.parity == 1) ? size_t(block.x) * 9 * a.meas_classes * sizeof(cx<R>) : 0;
 }
 
+// The kernel a slice launch uses: the class-splitting form for measured
+// parity-1 slices of two-layer lattices, else the form built for `waves`.
+template <int D, int PREC>
+static const void *update_fn(int waves, const UpdateArgs &a)
+{
+    if (a.meas != nullptr && a.parity == 1 && a.meas_classes == 3)
+        return reinterpret_cast<const void *>(&update_kernel<D, PREC, kDefaultWaves, 3>);
+    // parity-0 slices of a measured sweep measure nothing and use this kernel
+    if (a.meas != nullptr && a.meas_classes != 1 && a.meas_classes != 3) return nullptr;
+    if constexpr (D == 4) {
+        if (waves == 3) return reinterpret_cast<const void *>(&update_kernel<D, PREC, 3>);
+        if constexpr (PREC == kFP32_18 || PREC == kFP32_12)
+            if (waves == 4) return reinterpret_cast<const void *>(&update_kernel<D, PREC, 4>);
+    }
+    if (waves != kDefaultWaves) return nullptr;
+    return reinterpret_cast<const void *>(&update_kernel<D, PREC, kDefaultWaves>);
+}
+
+// Per-block LDS limit of the current device (queried once per device).
+static size_t lds_limit()
+{
+    static size_t cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+        cached[dev] = size_t(v);
+    }
+    return cached[dev];
+}
+
+template <int D, int PREC>
+static hipError_t update_lds_t(int waves, dim3 block, const UpdateArgs &a, size_t *need, size_t *limit)
+{
+    const void *fn = update_fn<D, PREC>(waves, a);
+    if (!fn) return hipErrorInvalidValue;
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return e;
+    *need = attr.sharedSizeBytes + update_lds_bytes<PREC>(block, a);
+    *limit = lds_limit();
+    return hipSuccess;
+}
+
 template <int D, int PREC>
 static hipError_t launch_update_t(int waves, dim3 grid, dim3 block, hipStream_t st, const UpdateArgs &a)
 {
-    const size_t lds = update_lds_bytes<PREC>(block, a);
-    if (a.meas != nullptr && a.parity == 1 && a.meas_classes == 3) {
-        // measured slice of a two-layer lattice: the class-splitting kernel
-        hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves, 3>), grid, block, lds, st, a);
-        return hipGetLastError();
-    }
-    // parity-0 slices of a measured sweep measure nothing and use this kernel
-    if (a.meas != nullptr && a.meas_classes != 1 && a.meas_classes != 3) return hipErrorInvalidValue;
-    if constexpr (D == 4) {
-        if (waves == 3) {
-            hipLaunchKernelGGL((update_kernel<D, PREC, 3>), grid, block, lds, st, a);
-            return hipGetLastError();
-        }
-        if constexpr (PREC == kFP32_18 || PREC == kFP32_12) {
-            if (waves == 4) {
-                hipLaunchKernelGGL((update_kernel<D, PREC, 4>), grid, block, lds, st, a);
-                return hipGetLastError();
-            }
-        }
-    }
-    if (waves != kDefaultWaves) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((update_kernel<D, PREC, kDefaultWaves>), grid, block, lds, st, a);
-    return hipGetLastError();
+    const void *fn = update_fn<D, PREC>(waves, a);
+    if (!fn) return hipErrorInvalidValue;
+    UpdateArgs args = a;
+    void *params[] = {&args};
+    return hipLaunchKernel(fn, grid, block, params, update_lds_bytes<PREC>(block, a), st);
 }
 
 template <int D>
@@ -547,6 +574,30 @@ static hipError_t launch_update_d(int prec, int waves, dim3 grid, dim3 block, hi
     case kFP32_18: return launch_update_t<D, kFP32_18>(waves, grid, block, st, a);
     case kFP32_12: return launch_update_t<D, kFP32_12>(waves, grid, block, st, a);
     case kFP64_12: return launch_update_t<D, kFP64_12>(waves, grid, block, st, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D>
+static hipError_t update_lds_d(int prec, int waves, dim3 block, const UpdateArgs &a, size_t *need, size_t *limit)
+{
+    switch (prec) {
+    case kFP64_18: return update_lds_t<D, kFP64_18>(waves, block, a, need, limit);
+    case kFP32_18: return update_lds_t<D, kFP32_18>(waves, block, a, need, limit);
+    case kFP32_12: return update_lds_t<D, kFP32_12>(waves, block, a, need, limit);
+    case kFP64_12: return update_lds_t<D, kFP64_12>(waves, block, a, need, limit);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t update_lds(int D, int prec, int waves, dim3 block, const UpdateArgs &a, size_t *need, size_t *limit)
+{
+    switch (D) {
+    case 2: return update_lds_d<2>(prec, waves, block, a, need, limit);
+    case 3: return update_lds_d<3>(prec, waves, block, a, need, limit);
+    case 4: return update_lds_d<4>(prec, waves, block, a, need, limit);
+    case 5: return update_lds_d<5>(prec, waves, block, a, need, limit);
+    case 6: return update_lds_d<6>(prec, waves, block, a, need, limit);
     default: return hipErrorInvalidValue;
     }
 }

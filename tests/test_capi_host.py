@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_0904_0642_amd as su3hb
@@ -84,6 +85,26 @@ def test_batch_rejects_bad_replicas():
         su3hb.su3hb_batch_create(4, [((4, 4, 4, 3), 6.0, 1, su3hb.HOT)], su3hb.FP32_18)
     with pytest.raises(su3hb.SU3HBError):
         su3hb.su3hb_batch_create(4, [], su3hb.FP32_18)
+
+
+@pytest.mark.parametrize("ext", [(256, 256, 256, 64), (182, 182, 182, 182)])
+def test_batch_rejects_replica_beyond_32bit_link_ids(ext):
+    # fewer than 2^32 sites but at least 2^32 links: the 32-bit Philox link id
+    # would wrap (colliding random streams), so the replica is refused before
+    # any device call (this host has no GPU)
+    assert int(np.prod(ext)) < 2 ** 32 <= 4 * int(np.prod(ext))
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        su3hb.su3hb_batch_create(4, [((4, 4, 4, 4), 6.0, 1, su3hb.HOT), (ext, 6.0, 2, su3hb.HOT)],
+                                 su3hb.FP32_12)
+    assert ei.value.code == su3hb.EINVAL
+    assert "replica 1" in str(ei.value) and "2^32 links" in str(ei.value)
+
+
+def test_init_rejects_beyond_32bit_link_ids():
+    p = su3hb.make_params([256, 256, 256, 64], precision=su3hb.FP32_12)
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        su3hb.su3hb_init_lattice(p)
+    assert ei.value.code == su3hb.EINVAL and "2^32 links" in str(ei.value)
 
 
 def test_no_cpu_fallback_in_package():

@@ -1,0 +1,64 @@
+"""The kernels' elementary functions of a Philox uniform u = (r+1)/2^32
+(device_math.h: log_unit, cos2_turn, sincos_turn), compiled for the host
+from the same source and compared with mpmath at 200 bits: ln u to 2 ulp,
+cos^2(2 pi u), sin and cos(2 pi u) to 2e-16 absolute in FP64 and 3e-7 in
+FP32.  The words cover the ends of the range, the quarter-turn boundaries
+of the reductions and random words."""
+import os
+import subprocess
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_0904_0642_amd", "csrc")
+SRC = os.path.join(ROOT, "tests", "device_math_host.cpp")
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("dm") / "device_math_host")
+    r = subprocess.run(["hipcc", "-O2", "-std=c++17", "-I" + CSRC, "-I" + os.path.join(ROOT, "include"), SRC,
+                        "-o", out], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return out
+
+
+def words():
+    rng = np.random.default_rng(7)
+    w = list(rng.integers(0, 2 ** 32, size=3000, dtype=np.uint64))
+    w += [0, 1, 2, 3, 2 ** 32 - 1, 2 ** 32 - 2, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + 1]
+    # u near k/8 (t = 4u near k/2: the switch between quarter turns) and
+    # near 2^-j (the binades of the logarithm's reduction), and m near sqrt(1/2)
+    for k in range(1, 8):
+        c = k * 2 ** 29 - 1
+        w += [c - 1, c, c + 1]
+    for j in range(1, 32):
+        c = 2 ** (32 - j) - 1
+        w += [c - 1, c, c + 1]
+        s = int(round(2 ** 32 * 0.7071067811865476 / 2 ** j)) - 1
+        w += [s - 1, s, s + 1]
+    return [int(x) for x in w if 0 <= int(x) < 2 ** 32]
+
+
+def test_elementary_functions_of_a_uniform(exe):
+    ws = words()
+    r = subprocess.run([exe], input="\n".join(map(str, ws)) + "\n", capture_output=True, text=True, check=True)
+    rows = [[float.fromhex(v) for v in line.split()] for line in r.stdout.strip().splitlines()]
+    assert len(rows) == len(ws)
+    mp.mp.prec = 200
+    worst = np.zeros(6)
+    for w, (lg, c2, sd, cd, sf, cf) in zip(ws, rows):
+        u = (mp.mpf(w) + 1) / 2 ** 32
+        ln = mp.log(u)
+        th = 2 * mp.pi * u
+        s, c = mp.sin(th), mp.cos(th)
+        ulp = np.spacing(abs(float(ln))) if ln != 0 else 2.0 ** -1074
+        err = [abs(lg - ln) / ulp if ln != 0 else abs(lg), abs(c2 - c * c), abs(sd - s), abs(cd - c),
+               abs(sf - s), abs(cf - c)]
+        worst = np.maximum(worst, [float(e) for e in err])
+    print("max errors: log %.2f ulp, cos^2 %.2e, sin/cos f64 %.2e %.2e, f32 %.2e %.2e" % tuple(worst))
+    assert worst[0] <= 2.0
+    assert worst[1] <= 2e-16 and worst[2] <= 2e-16 and worst[3] <= 2e-16
+    assert worst[4] <= 3e-7 and worst[5] <= 3e-7

@@ -41,9 +41,9 @@ def parities(ext):
     return (par & 1).astype(np.int8)
 
 
-def sampled_sweep_parity(oracle_mod, ext, prec, beta, slices, tol):
-    say(f"case full size ext={ext} prec={prec} beta={beta}")
-    g = su3hb.Lattice(ext, precision=prec, seed=1)
+def sampled_sweep_parity(oracle_mod, ext, prec, beta, slices, tol, nlat=1, mask=0):
+    say(f"case full size ext={ext} nlat={nlat} mask={mask:b} prec={prec} beta={beta}")
+    g = su3hb.Lattice(ext, nlat=nlat, dlt_mask=mask, precision=prec, seed=1)
     g.autotune(400)
     say(f"  launch {g.get_launch()}")
     L0 = g.get_links()
@@ -54,19 +54,20 @@ def sampled_sweep_parity(oracle_mod, ext, prec, beta, slices, tol):
     # the running action kept during the sweep equals a recomputation
     say(f"  running trace {t0 + st['dtrace']:.10f} recomputed {t1:.10f}")
     rel = abs(t0 + st["dtrace"] - t1) / abs(t1)
-    assert rel < (1e-11 if prec == su3hb.FP64_18 else 1e-5)
+    fp64 = prec in (su3hb.FP64_18, su3hb.FP64_12)
+    assert rel < (1e-11 if fp64 else 1e-5)
     # every link still in SU(3)
     u = L1.reshape(-1, 3, 3)
     for c0 in range(0, u.shape[0], 1 << 22):
         blk = u[c0:c0 + (1 << 22)]
         d = np.abs(np.einsum("nij,nkj->nik", blk, blk.conj()) - np.eye(3)).max()
-        assert d < (1e-12 if prec == su3hb.FP64_18 else 1e-6)
+        assert d < (1e-12 if fp64 else 1e-6)
     del u
 
     par = parities(ext)
     D = len(ext)
     rng = np.random.default_rng(2024)
-    o = oracle_mod.Lattice(ext, seed=1, threads=16)
+    o = oracle_mod.Lattice(list(ext), nlat=nlat, dlt_mask=mask, seed=1, threads=16)
     state = L0.copy()
     order = [(p, mu) for p in (0, 1) for mu in range(D)]
     worst = 0.0
@@ -75,26 +76,38 @@ def sampled_sweep_parity(oracle_mod, ext, prec, beta, slices, tol):
             o.set_links(state)
             o.sweep_counter = 0
             sites = rng.choice(np.flatnonzero(par == p), size=NSAMPLE, replace=False)
-            for s in sites:
-                o.update_link(0, int(s), mu, beta, beta, 8)
-                d = float(np.abs(o.get_link(0, int(s), mu) - L1[0, s, mu]).max())
+            layers = rng.integers(0, nlat, size=NSAMPLE)
+            for s, lay in zip(sites, layers):
+                o.update_link(int(lay), int(s), mu, beta, beta, 8)
+                d = float(np.abs(o.get_link(int(lay), int(s), mu) - L1[lay, s, mu]).max())
                 worst = max(worst, d)
             say(f"  slice (p={p}, mu={mu}): {NSAMPLE} sampled links, max |dU| so far {worst:.3e}")
         # the slice is done: its links take the GPU's values
-        mask = par == p
-        state[0, mask, mu] = L1[0, mask, mu]
+        mask_p = par == p
+        state[:, mask_p, mu] = L1[:, mask_p, mu]
     assert worst <= tol
     g.close()
+
+
+ALL_SLICES = {(p, mu) for p in (0, 1) for mu in range(4)}
 
 
 @pytest.mark.timeout(300)
 def test_48x48x48x48_fp64(oracle_mod):
     ext = (48, 48, 48, 48)
-    all_slices = {(p, mu) for p in (0, 1) for mu in range(4)}
-    sampled_sweep_parity(oracle_mod, ext, su3hb.FP64_18, 6.2, all_slices, 1e-10)
+    sampled_sweep_parity(oracle_mod, ext, su3hb.FP64_18, 6.2, ALL_SLICES, 1e-10)
 
 
-@pytest.mark.timeout(400)
+@pytest.mark.timeout(600)
 def test_64x64x64x64_fp32_12(oracle_mod):
     ext = (64, 64, 64, 64)
-    sampled_sweep_parity(oracle_mod, ext, su3hb.FP32_12, 6.2, {(0, 0), (1, 3)}, 1e-4)
+    sampled_sweep_parity(oracle_mod, ext, su3hb.FP32_12, 6.2, ALL_SLICES, 1e-4)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec,tol", [(su3hb.FP64_18, 1e-10), (su3hb.FP32_18, 1e-4), (su3hb.FP32_12, 1e-4)])
+def test_double_layered_2x24x24x24x8(oracle_mod, prec, tol):
+    # the double-layered torus of two 24^3 x 8 layers glued in every
+    # direction at beta = 5.69, in the launch shape the benchmark uses:
+    # sampled links of both layers in all eight slices of one sweep
+    sampled_sweep_parity(oracle_mod, (24, 24, 24, 8), prec, 5.69, ALL_SLICES, tol, nlat=2, mask=0b1111)

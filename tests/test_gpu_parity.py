@@ -482,3 +482,86 @@ def test_fused_measurement_equals_plaquette_kernel(ext, prec, tol):
     d = np.abs(fused[good] - sep[good]) / np.maximum(1.0, np.abs(sep[good]))
     say(f"  fused vs kernel max rel diff = {d.max():.3e}")
     assert d.max() <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [(su3hb.FP64_18, TOL64), (su3hb.FP32_18, TOL32), (su3hb.FP32_12, TOL32)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_replicas_match_oracle(oracle_mod, prec, tol, mode):
+    # a mixed batch (own extents, couplings, seeds and starts per replica):
+    # every replica after one batched sweep equals the oracle run on that
+    # replica alone, link by link, with the integer counters summed over the
+    # replicas bit-exact; mode 0 replays per-slice launches, mode 1 is the
+    # persistent launch.  FP32 storage starts the oracle from the FP32-rounded
+    # links the GPU holds.
+    reps = [((8, 8, 8, 8), 5.7, 101, su3hb.HOT), ((6, 4, 4, 2), 6.3, 202, su3hb.HOT),
+            ((4, 4, 4, 4), 5.5, 303, su3hb.COLD), ((12, 6, 4, 8), 6.05, 404, su3hb.HOT)]
+    say(f"case batch of {len(reps)} prec={prec} mode={mode}")
+    b = su3hb.Batch(4, reps, precision=prec)
+    oracles = []
+    for r, (ext, beta, seed, start) in enumerate(reps):
+        o = oracle_mod.Lattice(list(ext), seed=seed, threads=8)
+        if start == su3hb.COLD:
+            o.cold_start()
+        else:
+            o.hot_start()
+        if prec == su3hb.FP64_18:
+            assert maxdiff(b.get_links(r), o.get_links()) <= 1e-12, r
+        else:
+            o.set_links(b.get_links(r))
+        oracles.append(o)
+    st_b = b.sweep(n_hit=8, n_sweeps=1, mode=mode, stats=True)
+    att = np.zeros(3, dtype=np.int64)
+    acc = np.zeros(3, dtype=np.int64)
+    worst = 0.0
+    for r, (ext, beta, seed, start) in enumerate(reps):
+        st_o = oracles[r].sweep(beta, nhit=8, nsweeps=1)
+        att += np.array(st_o["attempts"])
+        acc += np.array(st_o["accepts"])
+        d = maxdiff(b.get_links(r), oracles[r].get_links())
+        say(f"  replica {r} {ext} beta={beta}: max |dU| = {d:.3e}")
+        worst = max(worst, d)
+    assert worst <= tol
+    assert list(st_b["attempts"]) == list(att)
+    assert list(st_b["accepts"]) == list(acc)
+    assert st_b["link_updates"] == sum(4 * int(np.prod(e)) for e, *_ in reps)
+    # per-replica plaquettes of the batch against the oracle's
+    pb = b.plaquette()
+    for r, (ext, beta, seed, start) in enumerate(reps):
+        po = oracles[r].plaquette(beta)
+        rt = 1e-12 if prec == su3hb.FP64_18 else 1e-5
+        assert np.allclose(pb[r][[0, 1, 2, 5]], po[[0, 1, 2, 5]], rtol=rt, atol=0), r
+
+
+@pytest.mark.parametrize("prec,tol", [(su3hb.FP64_18, TOL64), (su3hb.FP32_18, TOL32), (su3hb.FP32_12, TOL32),
+                                      (su3hb.FP64_12, TOL64)])
+@pytest.mark.parametrize("block", [64, 256])
+def test_double_layered_multiblock_matches_oracle(oracle_mod, prec, tol, block):
+    # a double-layered torus glued in every direction with beta0 != beta1 on
+    # a lattice whose slices span several blocks: 2 x 720 links per slice,
+    # 720 not a multiple of 64 (the last tile of each slab is partial) nor of
+    # the block, so the layer boundary falls inside a block.  Per link after
+    # one sweep from a shared start (FP32: the GPU's rounded start), the
+    # running action, the counters, and the fused two-layer measurement of a
+    # second sweep against the oracle's plaquettes of the same links.
+    ext, b0, b1 = [6, 10, 6, 4], 5.5, 6.2
+    g, o = pair(oracle_mod, ext, nlat=2, mask=0b1111, prec=prec, seed=17)
+    g.set_launch(block, 1, 2)
+    if prec != su3hb.FP64_18:
+        o.set_links(g.get_links())
+    st_g = g.sweep(b0, b1, n_hit=8, n_sweeps=1, stats=True)
+    st_o = o.sweep(b0, b1, nhit=8, nsweeps=1)
+    d = maxdiff(g.get_links(), o.get_links())
+    say(f"  DLT {ext} block={block} prec={prec}: max |dU| after 1 sweep = {d:.3e}")
+    assert d <= tol
+    assert list(st_g["attempts"]) == list(st_o["attempts"])
+    assert list(st_g["accepts"]) == list(st_o["accepts"])
+    rel = 1e-9 if prec in (su3hb.FP64_18, su3hb.FP64_12) else 1e-4
+    assert abs(st_g["dtrace"] - st_o["dtrace"]) <= rel * max(1.0, abs(st_o["dtrace"]))
+    # second sweep measured inside the update (three LDS classes), compared
+    # with the oracle's measurement of the GPU's resulting links
+    series = g.sweep_measure(b0, b1, n_hit=8, n_sweeps=1)
+    o.set_links(g.get_links())
+    po = o.plaquette(b0, b1)
+    rt = 1e-12 if prec in (su3hb.FP64_18, su3hb.FP64_12) else 2e-6
+    say(f"  fused measurement {series[0]} oracle {po}")
+    assert np.allclose(series[0], po, rtol=rt, atol=0, equal_nan=True)

@@ -204,7 +204,8 @@ def test_long_run_gpu_vs_oracle(oracle_mod):
     mo, eo = jackknife_mean(np.array(so), 32)
     q = gaussian_difference_q(mg, eg, mo, eo)
     say(f"  4^4 beta=6: GPU {mg:.5f}({eg*1e5:.0f}) oracle {mo:.5f}({eo*1e5:.0f}) Q={q:.2f}")
-    assert abs(mg - mo) < 3 * np.hypot(eg, eo)
+    # two combined jackknife error bars
+    assert abs(mg - mo) < 2 * np.hypot(eg, eo)
 
 
 def test_acceptance_near_97_percent():
@@ -219,20 +220,145 @@ def test_acceptance_near_97_percent():
 
 def test_fp32_vs_fp64_same_plaquette():
     # FP32 link storage (FP64 heatbath, reunitarisation, accumulation) gives
-    # the same observables as FP64 within the statistical error of
-    # equal-length runs: total, spacelike and timelike plaquette and the
-    # action sum beta sum_p (1/3) Re Tr U_p
+    # the same observables as FP64 within the statistical error: total,
+    # spacelike and timelike plaquette and the action beta sum_p (1/3) Re Tr
+    # U_p.  Each precision runs four independent chains (seeds 10..13; the
+    # same seeds for every precision, which only correlates the chains and
+    # makes the test conservative), pooled as the mean of the four chain
+    # means with the error of that mean, so that no single reference chain's
+    # fluctuation decides the comparison.
     names = ("total", "spacelike", "timelike", "action")
     cols = (0, 1, 2, 5)
+    seeds = (10, 11, 12, 13)
     res = {}
     for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
-        lat = su3hb.Lattice([16, 16, 16, 16], seed=10, precision=prec)
-        lat.sweep(6.0, n_hit=8, n_sweeps=300)
-        ser = lat.sweep_measure(6.0, n_hit=8, n_sweeps=3000)
-        res[prec] = [jackknife_mean(ser[:, c], 32) for c in cols]
+        per = []
+        for sd in seeds:
+            lat = su3hb.Lattice([16, 16, 16, 16], seed=sd, precision=prec)
+            lat.sweep(6.0, n_hit=8, n_sweeps=300)
+            ser = lat.sweep_measure(6.0, n_hit=8, n_sweeps=4000)
+            lat.close()
+            per.append([jackknife_mean(ser[:, c], binned(ser[:, c])) for c in cols])
+        res[prec] = [(np.mean([p[k][0] for p in per]), np.sqrt(np.sum([p[k][1] ** 2 for p in per])) / len(per))
+                     for k in range(len(cols))]
     for prec in (su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
         for k, name in enumerate(names):
             (m, e), (m64, e64) = res[prec][k], res[su3hb.FP64_18][k]
             say(f"  16^4 beta=6.0 prec={prec} {name}: {m:.8g}({e:.2g}) vs FP64 {m64:.8g}({e64:.2g}), "
                 f"{(m - m64) / np.hypot(e, e64):+.2f} sigma")
-            assert abs(m - m64) < 3 * np.hypot(e, e64)
+            assert abs(m - m64) < 2 * np.hypot(e, e64)
+
+
+def binned(series, nmax=32, nmin=8):
+    """Jackknife bins of at least 4 tau_int sweeps each (shorter bins are
+    correlated and underestimate the error), between nmin and nmax bins."""
+    tau = tau_int(series)[0]
+    return int(max(nmin, min(nmax, len(series) // max(1, int(np.ceil(4 * tau))))))
+
+
+def test_config3_double_layered_fp32_error_per_observable(oracle_mod):
+    # two 24^3 x 8 layers glued in every direction, beta = 5.69, hot start
+    # from seed 1, 500 sweeps measured after every sweep: FP32-18 and FP32-12
+    # storage (FP64 Kennedy-Pendleton draw, reunitarisation and accumulation)
+    # against the FP64 oracle's chain from the same seed, per observable
+    # (total, spacelike, timelike, layer 0, layer 1, the beta-weighted action);
+    # the FP64-18 GPU chain is compared the same way.  The first 100 sweeps
+    # are thermalisation; errors are jackknife errors of the rest, in bins of
+    # at least 4 tau_int.
+    ext, beta, nsw, ntherm = (24, 24, 24, 8), 5.69, 500, 100
+    names = ("total", "spacelike", "timelike", "layer 0", "layer 1", "action")
+    o = oracle_mod.Lattice(list(ext), nlat=2, dlt_mask=0b1111, seed=1, threads=16)
+    o.hot_start()
+    ser_o = []
+    for _ in range(nsw):
+        o.sweep(beta, nhit=8, nsweeps=1)
+        ser_o.append(o.plaquette(beta))
+    ser_o = np.array(ser_o)[ntherm:]
+    for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
+        lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0b1111, precision=prec, seed=1)
+        ser = lat.sweep_measure(beta, n_hit=8, n_sweeps=nsw)[ntherm:]
+        lat.close()
+        for k, name in enumerate(names):
+            nb = min(binned(ser[:, k]), binned(ser_o[:, k]))
+            m, e = jackknife_mean(ser[:, k], nb)
+            mo, eo = jackknife_mean(ser_o[:, k], nb)
+            z = (m - mo) / np.hypot(e, eo)
+            say(f"  2x24^3x8 beta={beta} prec={prec} {name}: {m:.8g}({e:.2g}) vs oracle {mo:.8g}({eo:.2g}), "
+                f"{z:+.2f} sigma ({nb} bins, tau_int {tau_int(ser[:, k])[0]:.1f} sweeps)")
+            assert abs(z) < 2.0, (prec, name)
+
+
+@pytest.mark.parametrize("beta", [5.7, 6.0])
+def test_config2_trajectory_and_first_flip(oracle_mod, beta):
+    # 16^4, hot start from seed 1, 200 sweeps with the plaquette after every
+    # sweep, GPU against the oracle from the same start and random numbers.
+    # The two chains follow each other to rounding until rounding flips an
+    # accept/reject decision (Sec. 3).  The first sweep whose counters differ
+    # is replayed on the oracle slice by slice; in the first slice whose
+    # links differ from the GPU's by more than rounding every differing link
+    # is a flipped decision, and its distance from the acceptance threshold
+    # R4^2 - (1 - delta/2) is printed.  Over the run the mean plaquettes agree
+    # within two combined jackknife error bars.
+    ext, nsw, ntherm = (16, 16, 16, 16), 200, 50
+    g = su3hb.Lattice(ext, seed=1)
+    o = oracle_mod.Lattice(list(ext), seed=1, threads=16)
+    o.hot_start()
+    first = None
+    pg, po, dmax = [], [], []
+    prev_g, prev_o = g.get_links(), o.get_links()
+    for k in range(nsw):
+        st_g = g.sweep(beta, n_hit=8, n_sweeps=1, stats=True)
+        st_o = o.sweep(beta, nhit=8, nsweeps=1)
+        pg.append(g.plaquette(beta)[0])
+        po.append(o.plaquette(beta)[0])
+        if first is None:
+            cur_g, cur_o = g.get_links(), o.get_links()
+            dmax.append(float(np.abs(cur_g - cur_o).max()))
+            same = (list(st_g["attempts"]) == list(st_o["attempts"])
+                    and list(st_g["accepts"]) == list(st_o["accepts"]))
+            if not same:
+                first = (k, prev_o, cur_g)
+            prev_g, prev_o = cur_g, cur_o
+    pg, po = np.array(pg), np.array(po)
+    say(f"  16^4 beta={beta}: max |dU| GPU vs oracle per sweep until the first flip: "
+        f"{' '.join(f'{d:.1e}' for d in dmax[:12])}{' ...' if len(dmax) > 12 else ''}")
+    say(f"  per-sweep |d<P>| max over the first 10 sweeps: {np.abs(pg[:10] - po[:10]).max():.2e}")
+    if first is None:
+        say(f"  no accept/reject decision differs in {nsw} sweeps")
+    else:
+        k, before_o, after_g = first
+        par = np.zeros(int(np.prod(ext)), dtype=np.int64)
+        idx = np.arange(par.size)
+        stride = 1
+        for n in ext:
+            par += (idx // stride) % n
+            stride *= n
+        par &= 1
+        o2 = oracle_mod.Lattice(list(ext), seed=1, threads=16)
+        o2.set_links(before_o)
+        o2.sweep_counter = k
+        flips = []
+        for p in (0, 1):
+            for mu in range(4):
+                state = o2.get_links()
+                o2.update_slice(p, mu, beta, nhit=8)
+                res = o2.get_links()
+                sites = np.flatnonzero(par == p)
+                dd = np.abs(res[0, sites, mu] - after_g[0, sites, mu]).reshape(len(sites), -1).max(axis=1)
+                if (dd > 1e-8).any():
+                    o2.set_links(state)
+                    for s in sites[dd > 1e-8]:
+                        flips.append((p, mu, int(s), o2.link_margin(0, int(s), mu, beta, nhit=8)))
+                    break
+            if flips:
+                break
+        bound = max(1e-9, 100.0 * (dmax[k - 1] if k > 0 else 0.0))
+        say(f"  sweep {k} is the first with different counters; max |dU| before it {dmax[k - 1] if k else 0:.1e}; "
+            f"flipped links (parity, mu, site, |margin|) = {flips[:4]}")
+        assert flips, "counters differ but no link of the sweep differs"
+        # a decision flips only within rounding of the threshold
+        assert min(f[3] for f in flips) < bound
+    mg, eg = jackknife_mean(pg[ntherm:], 15)
+    mo, eo = jackknife_mean(po[ntherm:], 15)
+    say(f"  <P> over sweeps {ntherm}..{nsw}: GPU {mg:.6f}({eg*1e6:.0f}) oracle {mo:.6f}({eo*1e6:.0f})")
+    assert abs(mg - mo) < 2 * np.hypot(eg, eo) or abs(mg - mo) < 1e-9

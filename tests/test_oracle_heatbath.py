@@ -98,3 +98,29 @@ def test_cold_start_staple_and_plaquette(oracle_mod):
         for s in (0, 1, L.V - 1):
             for mu in range(D):
                 assert np.array_equal(L.staple(0, s, mu, 6.0), 2 * (D - 1) * 6.0 * np.eye(3))
+
+
+def test_link_margin_observes_without_changing(oracle_mod):
+    # the threshold-margin probe (used to explain accept/reject flips between
+    # platforms, Sec. 3) changes neither the links nor the sweep counter
+    o = oracle_mod.Lattice([4, 4, 4, 4], seed=3)
+    o.hot_start()
+    o.sweep(5.8, nhit=8, nsweeps=2)
+    before, sw = o.get_links(), o.sweep_counter
+    m = o.link_margin(0, 5, 2, 5.8, nhit=8)
+    assert np.array_equal(o.get_links(), before) and o.sweep_counter == sw
+    assert 0.0 < m < 2.0
+    # beta = 0: every projection is degenerate, no proposal is evaluated
+    assert o.link_margin(0, 5, 2, 0.0, nhit=8) == float("inf")
+    # ordered start, beta = 6, D = 4: subgroup (0,1) of the first link sees
+    # W = 36 * 1, alpha = 24; the margin is at most that of its first
+    # proposal, recomputed here from the Philox words of the counter
+    # (link id, sweep 0, subgroup 0 hit 0 block 0, update stream)
+    c = oracle_mod.Lattice([4, 4, 4, 4], seed=9)
+    c.cold_start()
+    s, mu = 0, 0
+    words = oracle_mod.philox4x32_10([s * 4 + mu, 0, 0, 0], [9, 0])
+    u = [oracle_mod.uniform(w) for w in words]
+    delta = -(np.log(u[0]) + np.cos(2 * np.pi * u[1]) ** 2 * np.log(u[2])) / 24.0
+    m0 = abs(u[3] ** 2 - (1.0 - 0.5 * delta))
+    assert c.link_margin(0, s, mu, 6.0, nhit=1) <= m0 * (1 + 1e-12)
