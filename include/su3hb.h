@@ -250,6 +250,34 @@ int su3hb_batch_set_links(su3hb_batch *b, int replica, const double *host, size_
 
 void su3hb_batch_free(su3hb_batch *b);
 
+/* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): su3hb_sweep_measure
+ * without a handle and without any device or host allocation.
+ *
+ * n_sweeps sweeps of the lattice described by p, in the order and with the
+ * random numbers of su3hb_sweep (sweep indices sweep0 .. sweep0+n_sweeps-1,
+ * key p->seed), on the links at p->device_links (caller-owned device memory
+ * of p->device_bytes bytes in the library's layout, e.g. the buffer a handle
+ * created with su3hb_init_lattice on borrowed memory works on; p->start is
+ * ignored), issued on p->hip_stream.  series: NULL, or caller-owned DEVICE
+ * memory of 6 * n_sweeps doubles that receives, per sweep, the plaquettes in
+ * the layout of su3hb_plaquette.  The call only enqueues kernels (no memset,
+ * no copy, no synchronisation) and returns before the GPU finishes, so it can
+ * be captured into a graph.
+ *
+ * The kernels' counters, statistics and partial sums live in one static
+ * device array of 8 MiB per GPU, held until the process ends and shared by
+ * every call on that GPU: calls that overlap on one GPU (two streams, two
+ * threads) race.  Each call clears what must start at zero.  With series
+ * non-NULL the measurement needs D * ceil(nlat * V / 512) * (1 or 3)
+ * partial sums (3 for two layers) in that array, at most (8 MiB - 33 KiB) / 8;
+ * a larger lattice returns SU3HB_EINVAL (64^4 fits; 128^4 does not).  Other
+ * errors as su3hb_init_lattice and su3hb_sweep, all reported before any
+ * device work; the links are left unchanged then. */
+int su3hb_sweep_measure_static(const su3hb_params *p, double beta0, double beta1, int n_hit, int n_sweeps,
+                               uint64_t sweep0, double *series);
+
 /* Thread-local description of the last error ("" if none). */
 const char *su3hb_last_error(void);
 

@@ -77,6 +77,8 @@ _SIGS = {
     "su3hb_batch_get_links": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
     "su3hb_batch_set_links": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
     "su3hb_batch_free": (None, [C.c_void_p]),
+    "su3hb_sweep_measure_static": (C.c_int, [C.POINTER(su3hb_params), C.c_double, C.c_double, C.c_int, C.c_int,
+                                             C.c_uint64, C.c_void_p]),
     "su3hb_last_error": (C.c_char_p, []),
 }
 
@@ -263,6 +265,14 @@ def su3hb_batch_set_links(h, replica, flat):
 
 def su3hb_batch_free(h):
     lib().su3hb_batch_free(h)
+
+
+def su3hb_sweep_measure_static(params: su3hb_params, beta0, beta1, n_hit, n_sweeps, sweep0=0, series_ptr=None):
+    """Measured sweeps with no allocation: params.device_links holds the
+    links, series_ptr is a device address of 6 * n_sweeps doubles (or None).
+    Asynchronous on params.hip_stream."""
+    _check(lib().su3hb_sweep_measure_static(C.byref(params), float(beta0), float(beta1), int(n_hit),
+                                            int(n_sweeps), int(sweep0), series_ptr))
 
 
 # ---------------------------------------------------------------------------

@@ -536,6 +536,19 @@ __global__ void u64_zero_kernel(unsigned long long *p, int n)
     if (t < n) atomicExch(&p[t], 0ull);
 }
 
+// One replica descriptor, passed by value, written to device memory (so a
+// captured graph carries the descriptor in its kernel arguments).
+__global__ void rep_set_kernel(RepDesc r, RepDesc *dst)
+{
+    if (threadIdx.x == 0) *dst = r;
+}
+
+hipError_t launch_rep_set(hipStream_t st, const RepDesc &r, RepDesc *dst)
+{
+    hipLaunchKernelGGL(rep_set_kernel, dim3(1), dim3(64), 0, st, r, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_stats_zero(hipStream_t st, StatSlot *slots)
 {
     hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(kStatSlots), 0, st, slots);

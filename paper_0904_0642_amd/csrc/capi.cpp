@@ -686,6 +686,45 @@ int ensure_events(su3hb_lattice *L, size_t n)
     return SU3HB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of su3hb_sweep_measure_static: a file-scope device array, so that
+// call allocates nothing.  Each GPU holds its own copy until the process
+// ends; every call on a GPU shares it (calls that overlap on one GPU race).
+// Layout (byte offsets): the replica descriptor, the sweep counter, the
+// series cursor, the last plaquettes, the statistics slots, then the fused
+// measurement's per-block partial sums.
+constexpr size_t kScratchBytes = size_t(8) << 20;
+constexpr size_t kScrRep = 0, kScrSweep = 256, kScrCursor = 512, kScrPlaq = 768, kScrStats = 1024;
+constexpr size_t kScrMeas = kScrStats + sizeof(StatSlot) * kStatSlots;
+constexpr size_t kScratchMeasDoubles = (kScratchBytes - kScrMeas) / sizeof(double);
+static_assert(sizeof(RepDesc) <= kScrSweep - kScrRep, "replica descriptor overflows its scratch slot");
+static_assert(kScrMeas % 256 == 0, "partial sums start on a 256-byte boundary");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.  The host-side name `scratch` is not a
+// device address and is never passed to a kernel.
+int scratch_base(unsigned char **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SU3HB_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SU3HB_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SU3HB_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1146,5 +1185,107 @@ int su3hb_batch_set_links(su3hb_batch *L, int replica, const double *host, size_
 }
 
 void su3hb_batch_free(su3hb_batch *b) { destroy(b); }
+
+// ---------------------------------------------------------------------------
+// measured sweeps that allocate nothing
+
+int su3hb_sweep_measure_static(const su3hb_params *p, double beta0, double beta1, int n_hit, int n_sweeps,
+                               uint64_t sweep0, double *series)
+{
+    // every check comes before the first device call
+    if (!p) return fail(SU3HB_EINVAL, "params is NULL");
+    uint64_t V;
+    int rc = check_extents(p->nd, p->extents, &V);
+    if (rc) return rc;
+    if (p->nlat != 1 && p->nlat != 2) return fail(SU3HB_EINVAL, "nlat = %d, expected 1 or 2", p->nlat);
+    if (p->nlat == 1 && (p->dlt_mask != 0 || p->lat2test))
+        return fail(SU3HB_EINVAL, "dlt_mask and lat2test need nlat = 2");
+    if (p->dlt_mask >> p->nd) return fail(SU3HB_EINVAL, "dlt_mask has bits beyond direction %d", p->nd - 1);
+    if (p->precision < 0 || p->precision > 3) return fail(SU3HB_EINVAL, "unknown precision %d", p->precision);
+    if (double(p->nlat) * double(V) * p->nd > 4294967295.0)
+        return fail(SU3HB_EINVAL, "more than 2^32 links: the Philox counter holds a 32-bit link id");
+    rc = check_sweep_args(beta0, beta1, n_hit, n_sweeps);
+    if (rc) return rc;
+    if (sweep0 + uint64_t(n_sweeps) > (uint64_t(1) << 32))
+        return fail(SU3HB_EINVAL, "sweep %llu + %d passes 2^32: the Philox counter holds a 32-bit sweep index",
+                    (unsigned long long)sweep0, n_sweeps);
+    if (!p->device_links) return fail(SU3HB_EINVAL, "device_links is NULL: the links are the caller's");
+    if (reinterpret_cast<uintptr_t>(p->device_links) % 16)
+        return fail(SU3HB_EINVAL, "device buffer must be 16-byte aligned");
+    const size_t need_links = size_t(p->nlat) * p->nd * 2 * size_t(padded_half(uint32_t(V / 2))) *
+                              size_t(bytes_per_link(p->precision));
+    if (p->device_bytes < need_links)
+        return fail(SU3HB_EINVAL, "device buffer holds %zu bytes, the links need %zu", p->device_bytes, need_links);
+
+    // launch shape: 256-thread blocks, each XCD a contiguous run of blocks,
+    // 2 waves per SIMD (links are bit-identical for every shape)
+    constexpr int kBlock = 256;
+    RepDesc rep = make_rep(p->nd, p->extents, p->nlat, p->nlat == 2 ? p->dlt_mask : 0u, p->lat2test, p->seed,
+                           0.0, 0.0);
+    rep.upd_block0 = 0;
+    rep.upd_blocks = (rep.nlat * rep.Vh + kBlock - 1) / kBlock;
+    const int nc = p->nlat == 2 ? 3 : 1;
+    const size_t meas_doubles = size_t(p->nd) * rep.upd_blocks * size_t(nc);
+    if (series && meas_doubles > kScratchMeasDoubles)
+        return fail(SU3HB_EINVAL,
+                    "lattice too large for the static scratch: the measurement needs %zu partial sums, the scratch "
+                    "holds %zu (%zu bytes)",
+                    meas_doubles, kScratchMeasDoubles, kScratchBytes);
+    if (n_sweeps == 0) return SU3HB_OK;
+
+    unsigned char *base = nullptr;
+    rc = scratch_base(&base);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(p->hip_stream);
+    RepDesc *d_rep = reinterpret_cast<RepDesc *>(base + kScrRep);
+    uint32_t *d_sweep = reinterpret_cast<uint32_t *>(base + kScrSweep);
+    uint32_t *d_cursor = reinterpret_cast<uint32_t *>(base + kScrCursor);
+    double *d_plaq = reinterpret_cast<double *>(base + kScrPlaq);
+    StatSlot *d_stats = reinterpret_cast<StatSlot *>(base + kScrStats);
+    double *d_meas = reinterpret_cast<double *>(base + kScrMeas);
+
+    UpdateArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.links = p->device_links;
+    a.reps = d_rep;
+    a.nrep = 1;
+    a.nhit = n_hit;
+    a.order = 1;
+    a.beta0 = beta0;
+    a.beta1 = beta1;
+    a.meas_classes = nc;
+    a.sweep = d_sweep;
+    a.stats = d_stats;
+    a.total_blocks = rep.upd_blocks;
+    a.meas = series ? d_meas : nullptr;
+    const dim3 grid((rep.upd_blocks + 7) / 8 * 8), block(kBlock);
+    {
+        UpdateArgs m = a;
+        m.parity = 1;
+        size_t need = 0, limit = 0;
+        HIPCHK(update_lds(p->nd, p->precision, kDefaultWaves, block, m, &need, &limit));
+        if (limit == 0 || need > limit)
+            return fail(SU3HB_EUNSUPPORTED, "update launch needs %zu bytes of LDS per block, the device allows %zu",
+                        need, limit);
+    }
+    // set-up: no memset nodes (kernels clear what must start at zero)
+    HIPCHK(launch_rep_set(st, rep, d_rep));
+    HIPCHK(launch_counter_set(st, d_sweep, uint32_t(sweep0)));
+    HIPCHK(launch_counter_set(st, d_cursor, 0));
+    HIPCHK(launch_stats_zero(st, d_stats));
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        for (int par = 0; par < 2; ++par)
+            for (int mu = 0; mu < p->nd; ++mu) {
+                a.parity = par;
+                a.mu = mu;
+                HIPCHK(launch_update(p->nd, p->precision, kDefaultWaves, grid, block, st, a));
+            }
+        HIPCHK(launch_counter_add(st, d_sweep, 1));
+        if (series)
+            HIPCHK(launch_measure_finalize(st, d_meas, p->nd, rep.upd_blocks, nc, double(rep.V), int(rep.nlat), beta0,
+                                           beta1, d_plaq, series, d_cursor));
+    }
+    return SU3HB_OK;
+}
 
 }  // extern "C"

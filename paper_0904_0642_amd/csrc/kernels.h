@@ -48,6 +48,9 @@ hipError_t launch_unpack(int D, int prec, hipStream_t st, void *links, const Rep
 // non-negative double (Inf for non-finite input), folded into *maxdef
 hipError_t launch_validate(hipStream_t st, const double *src, uint64_t nmat, unsigned long long *maxdef);
 
+// write one replica descriptor (by value) to device memory
+hipError_t launch_rep_set(hipStream_t st, const RepDesc &r, RepDesc *dst);
+
 // statistics slots and counters
 hipError_t launch_stats_zero(hipStream_t st, StatSlot *slots);
 hipError_t launch_stats_reduce(hipStream_t st, const StatSlot *slots, StatSlot *out);

@@ -115,3 +115,14 @@ def test_no_cpu_fallback_in_package():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "liboracle" not in txt
+
+
+def test_static_scratch_rejects_oversized_measurement():
+    # su3hb_sweep_measure_static on 128^4: the per-block partial sums of the
+    # measurement exceed the static scratch; refused before any device work
+    # (a dummy, aligned device pointer that is never dereferenced)
+    p = su3hb.make_params([128, 128, 128, 128], precision=su3hb.FP32_12, device_links=C.c_void_p(1 << 20),
+                          device_bytes=1 << 40)
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        su3hb.su3hb_sweep_measure_static(p, 6.0, 6.0, 8, 1, 0, C.c_void_p(1 << 21))
+    assert ei.value.code == su3hb.EINVAL and "static scratch" in str(ei.value)
