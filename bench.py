@@ -205,52 +205,58 @@ def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int =
     return res
 
 
-def dlt_leg(n_hit: int, autotune_ms: int, nsweeps: int = 500, ntherm: int = 100):
+def dlt_leg(n_hit: int, autotune_ms: int, seeds=(1, 2, 3, 4), nmeas: int = 2000, ntherm: int = 200):
     """Double-layered torus: two 24^3 x 8 layers glued in all directions,
-    beta0 = beta1 = 5.69, hot start from seed 1, nsweeps sweeps with the
-    plaquettes measured after every sweep, in FP64-18, FP32-18 and FP32-12
-    storage from the same seed.  Each observable of the FP32 chains (total,
-    spacelike, timelike, per layer, the beta-weighted action) is compared with
-    the FP64-18 chain in units of the combined jackknife error (bins of at
-    least 4 tau_int) over the sweeps after ntherm; the FP64-18 path itself is
-    compared with the FP64 oracle in the test suite."""
+    beta0 = beta1 = 5.69, hot starts, plaquettes measured after every sweep,
+    in FP64-18, FP32-18 and FP32-12 storage, four independent chains (seeds)
+    per form of ntherm + nmeas sweeps.  Each observable (total, spacelike,
+    timelike, per layer, the beta-weighted action) is pooled over the chains
+    (mean of the chain means, error of that mean from the chains' jackknife
+    errors in bins of at least 4 tau_int), and each FP32 form's deviation
+    from FP64-18 is stated in units of the combined error; the FP64-18 path
+    itself is compared with the FP64 oracle in the test suite.  The rate is
+    over all timed sweeps of a form."""
     import torch
 
     import paper_0904_0642_amd as su3hb
     from paper_0904_0642_amd.analysis import jackknife_mean, tau_int
 
     def nbins(x):
-        # bins of at least 4 tau_int sweeps, 8 to 20 of them
-        return int(max(8, min(20, len(x) // max(1, int(np.ceil(4 * tau_int(x)[0]))))))
+        # bins of at least 4 tau_int sweeps, 8 to 32 of them
+        return int(max(8, min(32, len(x) // max(1, int(np.ceil(4 * tau_int(x)[0]))))))
+
+    def pooled(chs, c):
+        ms, es = zip(*[jackknife_mean(ch[:, c], nbins(ch[:, c])) for ch in chs])
+        return float(np.mean(ms)), float(np.sqrt(np.sum(np.square(es))) / len(ms))
 
     ext, beta = (24, 24, 24, 8), 5.69
     links = 2 * int(np.prod(ext)) * 4
     names = ("total", "spacelike", "timelike", "layer0", "layer1", "action")
-    res = {"lattice": "2 x 24^3 x 8, all directions glued", "beta": beta, "sweeps": nsweeps,
-           "thermalisation_sweeps": ntherm, "links_per_sweep": links, "unit": "link updates/s"}
-    ser = {}
+    res = {"lattice": "2 x 24^3 x 8, all directions glued", "beta": beta, "chains": len(seeds),
+           "sweeps_per_chain": ntherm + nmeas, "thermalisation_sweeps": ntherm, "links_per_sweep": links,
+           "unit": "link updates/s"}
+    chains = {}
     for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
-        lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0xF, precision=prec, seed=1)
-        if autotune_ms > 0:
-            lat.autotune(autotune_ms)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s = lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=nsweeps)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        ser[prec] = s[ntherm:]
-        res[PREC_NAME[prec]] = {"value": round(nsweeps * links / secs, 1),
-                                "launch": dict(zip(("block", "order", "waves"), lat.get_launch()))}
-        lat.close()
+        chains[prec], secs, launch = [], 0.0, None
+        for sd in seeds:
+            lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0xF, precision=prec, seed=sd)
+            if autotune_ms > 0:
+                lat.autotune(autotune_ms)
+            launch = dict(zip(("block", "order", "waves"), lat.get_launch()))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chains[prec].append(lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=ntherm + nmeas)[ntherm:])
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            lat.close()
         torch.cuda.empty_cache()
-    nb = {k: min(nbins(ser[p][:, c]) for p in ser) for c, k in enumerate(names)}
-    ref = {k: jackknife_mean(ser[su3hb.FP64_18][:, c], nb[k]) for c, k in enumerate(names)}
+        res[PREC_NAME[prec]] = {"value": round(len(seeds) * (ntherm + nmeas) * links / secs, 1), "launch": launch}
+    ref = {k: pooled(chains[su3hb.FP64_18], c) for c, k in enumerate(names)}
     res["fp64-18"]["observables"] = {k: [round(m, 9), float(f"{e:.3g}")] for k, (m, e) in ref.items()}
-    res["jackknife_bins"] = nb
     for prec in (su3hb.FP32_18, su3hb.FP32_12):
         obs, dev = {}, {}
         for c, k in enumerate(names):
-            m, e = jackknife_mean(ser[prec][:, c], nb[k])
+            m, e = pooled(chains[prec], c)
             obs[k] = [round(m, 9), float(f"{e:.3g}")]
             dev[k] = round((m - ref[k][0]) / np.hypot(e, ref[k][1]), 2)
         res[PREC_NAME[prec]]["observables"] = obs
@@ -380,12 +386,18 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
+    def done(what):
+        # one progress line per finished leg, on stderr (stdout carries the JSON line)
+        print(f"[bench] {what} done", file=sys.stderr, flush=True)
+
     main_leg = run_leg(args.workload, args.steps, args.warmup, args.n_hit, args.autotune_ms,
                        parse_launch(args.launch))
+    done(args.workload)
     legs = {}
     if args.compare and args.compare != args.workload:
         legs[args.compare] = run_leg(args.compare, args.steps, args.warmup, args.n_hit, args.autotune_ms,
                                      parse_launch(args.compare_launch))
+        done(args.compare)
 
     ext, prec, beta = WORKLOADS[args.workload]
     line = {
@@ -421,14 +433,19 @@ def main():
         }
     if not args.no_extra_legs:
         line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
+        done("batch")
         line["dlt_2x24^3x8"] = dlt_leg(args.n_hit, args.autotune_ms)
+        done("double-layered torus")
         line["precision_study"] = precision_study(args.n_hit)
+        done("precision study")
         line["overrelaxation_" + args.workload] = overrelax_leg(args.workload, args.steps, args.warmup,
                                                                 args.autotune_ms)
+        done("overrelaxation")
         for name in ("64^4-fp32-18", "48^4-fp64-12"):
             if name in (args.workload, args.compare):
                 continue
             leg = run_leg(name, args.steps, args.warmup, args.n_hit, args.autotune_ms)
+            done(name)
             line["full_size_" + name] = {
                 "value": round(leg["rate"], 1), "unit": "link updates/s",
                 "ms_per_step": round(leg["ms_per_step"], 4), "roofline": leg["roofline"],
@@ -437,6 +454,7 @@ def main():
             }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.n_hit)
+        done("cpu baseline")
     print(json.dumps(line), flush=True)
 
 

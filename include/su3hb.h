@@ -156,12 +156,15 @@ int su3hb_sweep_measure(su3hb_lattice *lat, double beta0, double beta1, int n_hi
  * Synchronises. */
 int su3hb_plaquette(su3hb_lattice *lat, double beta0, double beta1, double out[6]);
 
-/* Copy the links to host memory in the canonical FP64 layout; n must equal
- * nlat*V*D*18.  FP32 modes are widened; 12-real links get their third row
- * rebuilt.  Synchronises. */
+/* Copy the links to host memory in the canonical FP64 layout, the paper's
+ * own array of links indexed by site number and direction (the A(n_s, nd)
+ * link arrays of Sec. 2) with the 18 reals of the 3x3 complex matrix
+ * innermost and the layer outermost; n must equal nlat*V*D*18.  FP32 modes
+ * are widened; 12-real links get their third row rebuilt.  Synchronises. */
 int su3hb_get_links(const su3hb_lattice *lat, double *host, size_t n);
 
-/* Replace the links from host memory in the canonical layout.  Every matrix
+/* Replace the links from host memory in the canonical layout (as
+ * su3hb_get_links: the A(n_s, nd) arrays of Sec. 2).  Every matrix
  * is checked on the GPU first: a NaN/Inf entry, or max|U U^dag - 1| or
  * |det U - 1| above 1e-10 (FP64 modes) / 1e-6 (FP32 modes) returns SU3HB_ENOTSU3
  * and leaves the lattice unchanged.  Synchronises. */
@@ -170,6 +173,9 @@ int su3hb_set_links(su3hb_lattice *lat, const double *host, size_t n);
 /* Seed and sweep counter: with the links they are the whole Markov-chain
  * state, so get_links + get_state ... set_links + set_state resumes a run
  * exactly (the random numbers are a function of seed, sweep and link).  The
+ * seed plays the part of the seed pair iseed1, iseed2 of mc.par (Sec. 2.3);
+ * the sweep counter stands for the position of the paper's sequential
+ * generator, which a counter-based generator does not have.  The
  * sweep index of the Philox counter is 32 bits: set_state rejects sweep >=
  * 2^32 and a sweep call that would pass 2^32 returns SU3HB_EINVAL. */
 int su3hb_get_state(const su3hb_lattice *lat, uint64_t *seed, uint64_t *sweep);
@@ -185,8 +191,11 @@ int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
  * multiple of 64 half-sites); 4 = as 2, walking the block's chunk of the
  * plane slowest and x_{D-2} in the middle; 5 = as 3, walking the x_{D-2}
  * tiles before the chunks of the plane; 6 = as 3, with all waves of a block
- * along x_{D-2}.  Where an order does not apply a lower one that does is
- * used (4 and 2 fall back to 1; 3, 5 and 6 to 2 or 1).
+ * along x_{D-2}; 7 (D = 4) = each wave covers a 4D tile of 8 half-sites along
+ * x_0 by 2 x 2 x 2 along x_1, x_2, x_3, the waves of a block stacked along
+ * x_2, each XCD walking one x_3 slab (n_0/2 a multiple of 8, n_2 of twice
+ * the waves per block, n_3 of 16).  Where an order does not apply a lower one
+ * that does is used (4 and 2 fall back to 1; 3, 5 and 6 to 2 or 1; 7 to 1).
  * Adding 8 to an order makes every second slice of a sweep walk each XCD's
  * blocks last to first, so a slice starts on the links the slice before it
  * read last.  waves: minimum waves per SIMD the kernel is compiled for: 2;

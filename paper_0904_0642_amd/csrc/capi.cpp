@@ -312,6 +312,18 @@ bool cube_order_ok(const su3hb_lattice *L, int block, int order)
     return plane % 64u == 0 && n2 % t2 == 0 && nl % (8u * t3) == 0;
 }
 
+// Order 7 (4D wave tiles, D = 4): one single-layer lattice with n_0/2 a
+// multiple of 8, n_2 of twice the waves per block and n_3 of 16 (one x_3 slab
+// of whole tiles per XCD).
+bool tile4_order_ok(const su3hb_lattice *L, int block)
+{
+    if (L->batch || L->nrep != 1 || L->nd != 4) return false;
+    const RepDesc &r = L->reps[0];
+    if (r.nlat != 1) return false;
+    const uint32_t nw = uint32_t(block) / 64u;
+    return (uint32_t(r.n[0]) / 2u) % 8u == 0 && uint32_t(r.n[2]) % (2u * nw) == 0 && uint32_t(r.n[3]) % 16u == 0;
+}
+
 // Flag added to an order: alternate slices walk every XCD's blocks backwards.
 constexpr int kOrderReverse = 8;
 
@@ -319,6 +331,7 @@ constexpr int kOrderReverse = 8;
 int base_order(const su3hb_lattice *L)
 {
     const int o = L->order & ~kOrderReverse;
+    if (o == 7 && !tile4_order_ok(L, L->block)) return 1;
     if (is_cube_order(o) && !cube_order_ok(L, L->block, o)) return slab_order_ok(L, L->block) ? 2 : 1;
     if ((o == 2 || o == 4) && !slab_order_ok(L, L->block)) return 1;
     return o;
@@ -336,7 +349,13 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
     a.nhit = nhit;
     a.use_rep_beta = L->batch ? 1 : 0;
     a.order = base_order(L);
-    if (a.order >= 2) {
+    if (a.order == 7) {
+        const RepDesc &r = L->reps[0];
+        a.n0h = uint32_t(r.n[0]) / 2u;
+        a.n1 = uint32_t(r.n[1]);
+        a.n2 = uint32_t(r.n[2]);
+        a.slab = uint32_t(r.n[3]) / 16u;
+    } else if (a.order >= 2) {
         const RepDesc &r = L->reps[0];
         const uint32_t nl = uint32_t(r.n[L->nd - 1]), n2 = uint32_t(r.n[L->nd - 2]);
         a.n2 = n2;
@@ -663,8 +682,8 @@ int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
-    if (order < 0 || (order & ~kOrderReverse) > 6)
-        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 6, optionally + %d", order, kOrderReverse);
+    if (order < 0 || (order & ~kOrderReverse) > 7)
+        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 7, optionally + %d", order, kOrderReverse);
     if (waves != 2 && !(waves == 3 && L->nd == 4) && !(waves == 4 && L->nd == 4 && is_fp32(L->prec)))
         return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4, or 4 for D = 4 with FP32 links", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -950,8 +969,9 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
         if (waves >= 3 && L->nd != 4) continue;
         if (waves == 4 && !is_fp32(L->prec)) continue;
         for (int block : {256, 128, 64})
-            for (int order : {0, 1, 2, 3, 4, 5, 6}) {
+            for (int order : {0, 1, 2, 3, 4, 5, 6, 7}) {
                 if ((order == 2 || order == 4) && !slab_order_ok(L, block)) continue;
+                if (order == 7 && !tile4_order_ok(L, block)) continue;
                 if (is_cube_order(order) && (block == 64 || !cube_order_ok(L, block, order))) continue;
                 cands.push_back(Shape{block, order, waves});
                 cands.push_back(Shape{block, order | kOrderReverse, waves});

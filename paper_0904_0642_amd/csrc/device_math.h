@@ -180,13 +180,44 @@ __device__ __forceinline__ void third_row(mat3<T> &u)
     u.e[2][2] = cx<T>{c2.re, -c2.im};
 }
 
+// 1/sqrt(x) for x >= 2^-1000: the hardware reciprocal square-root estimate
+// refined by two Newton steps y <- y + (y/2)(1 - x y^2), each of which about
+// doubles the number of correct bits; within about an ulp.
+__device__ __forceinline__ double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// sqrt(t) for t >= 0 in T: FP64 through rsqrt_refined (t below 2^-1000,
+// including 0, takes the library square root), FP32 the library one.
+template <typename T>
+__device__ __forceinline__ T sqrt_nonneg(T t);
+template <>
+__device__ __forceinline__ double sqrt_nonneg<double>(double t)
+{
+    return t >= 0x1p-1000 ? t * rsqrt_refined(t) : sqrt(t);
+}
+template <>
+__device__ __forceinline__ float sqrt_nonneg<float>(float t)
+{
+    return sqrtf(t);
+}
+
 // Gram-Schmidt on rows 0 and 1, then row 2 = conj(row0 x row1): det = 1.
+// The row norms are near 1 (links are unitary to rounding before the update
+// rotates them), inside the range of rsqrt_refined.
 __device__ __forceinline__ void reunitarize(mat3<double> &u)
 {
     double n0 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) n0 = fma(u.e[0][c].re, u.e[0][c].re, fma(u.e[0][c].im, u.e[0][c].im, n0));
-    n0 = 1.0 / sqrt(n0);
+    n0 = rsqrt_refined(n0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         u.e[0][c].re *= n0;
@@ -200,7 +231,7 @@ __device__ __forceinline__ void reunitarize(mat3<double> &u)
     double n1 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) n1 = fma(u.e[1][c].re, u.e[1][c].re, fma(u.e[1][c].im, u.e[1][c].im, n1));
-    n1 = 1.0 / sqrt(n1);
+    n1 = rsqrt_refined(n1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         u.e[1][c].re *= n1;
@@ -212,6 +243,12 @@ __device__ __forceinline__ void reunitarize(mat3<double> &u)
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
 // multiplies with the key bumped by a Weyl sequence between rounds.
+
+// a ^ b ^ c in one gfx950 three-input bit operation (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
@@ -225,7 +262,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         const uint64_t p0 = uint64_t(0xD2511F53u) * c.x, p1 = uint64_t(0xCD9E8D57u) * c.z;
         const uint32_t lo0 = uint32_t(p0), hi0 = uint32_t(p0 >> 32);
         const uint32_t lo1 = uint32_t(p1), hi1 = uint32_t(p1 >> 32);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        c = make_uint4(xor3(hi1, c.y, k0), lo1, xor3(hi0, c.w, k1), lo0);
     }
     return c;
 }

@@ -78,13 +78,15 @@ struct UpdateArgs {
     int mu;                      // direction being updated
     int nhit;                    // KP proposals per subgroup, at most; 0: overrelaxation
     int use_rep_beta;            // 1: couplings from RepDesc; 0: from beta0/beta1
-    int order;                   // 0 hardware, 1 XCD-contiguous, 2 and 4 XCD slabs, 3, 5 and 6 XCD slabs of 3D blocks
+    int order;                   // 0 hardware, 1 XCD-contiguous, 2 and 4 XCD slabs, 3, 5 and 6 XCD slabs of 3D blocks,
+                                 // 7 XCD slabs of 4D wave tiles
     int reverse;                 // 1: each XCD walks its blocks last to first (alternate slices)
     uint32_t slab;               // orders 2, 3: tiles of the last direction per XCD
     uint32_t cp;                 // orders 2, 3: blocks (order 3: waves) per (x_{D-2}, x_{D-1}) plane
     uint32_t n2;                 // orders 2, 3: extent of direction D-2
     uint32_t plane;              // order 3: half-sites of one (x_{D-2}, x_{D-1}) plane
     uint32_t tile2, tile3;       // order 3: waves of a block along x_{D-2} and x_{D-1}
+    uint32_t n0h, n1;            // order 7: n_0 / 2 and n_1
     double beta0, beta1;
     const uint32_t *sweep;       // device sweep counter
     StatSlot *stats;             // kStatSlots slots

@@ -15,6 +15,22 @@
 
 namespace su3hb {
 
+// 1/k for the norm k = sqrt(k2) of a projected SU(2) block; false for a
+// degenerate projection (k <= 1e-300), which no hit accepts.  Norms from
+// 2^-500 up take rsqrt_refined; smaller ones the exact square root, so the
+// degenerate test is the one of the definition.
+__device__ __forceinline__ bool inv_norm(double k2, double &ik)
+{
+    if (k2 >= 0x1p-1000) {
+        ik = rsqrt_refined(k2);
+        return true;
+    }
+    const double k = sqrt(k2);
+    if (!(k > 1e-300)) return false;
+    ik = 1.0 / k;
+    return true;
+}
+
 // U <- R_IJ(r) U and W <- R_IJ(r) W: the 2x2 matrix r mixes rows I and J.
 template <typename H, int I, int J>
 __device__ __forceinline__ void rotate_rows(mat3<H> &U, mat3<H> &W, const cx<H> &r00, const cx<H> &r01,
@@ -51,10 +67,9 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
     const double a1 = 0.5 * (double(W.e[I][J].im) + double(W.e[J][I].im));
     const double a2 = 0.5 * (double(W.e[I][J].re) - double(W.e[J][I].re));
     const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
-    const double k = sqrt(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))));
-    if (!(k > 1e-300)) return;  // degenerate projection: every hit rejected
     // alpha = 2k/3; the draw multiplies by 1/alpha = 1.5/k, computed once
-    const double ik = 1.0 / k;
+    double ik;
+    if (!inv_norm(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))), ik)) return;  // degenerate: every hit rejected
     const double inv_alpha = 1.5 * ik;
 
     // multi-hit Kennedy-Pendleton: delta = 1 - x0 ~ sqrt(delta) exp(-alpha delta),
@@ -82,9 +97,9 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
     const uint4 q = philox4x32_10(
         make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1) | 1u, kTagUpdate), k0, k1);
     const H x0 = H(x0d);
-    const H rad = H(sqrt(fmax(0.0, 1.0 - x0d * x0d)));
+    const H rad = sqrt_nonneg<H>(H(fmax(0.0, 1.0 - x0d * x0d)));
     const H cth = H(2.0 * u01(q.x) - 1.0);
-    const H sth = sqrt(max(H(0), H(1) - cth * cth));
+    const H sth = sqrt_nonneg<H>(max(H(0), H(1) - cth * cth));
     H sph, cph;
     sincos_turn<H>(u01(q.y), &sph, &cph);  // phi = 2 pi u
     const H x1 = rad * sth * cph, x2 = rad * sth * sph, x3 = rad * cth;
@@ -115,11 +130,10 @@ __device__ __forceinline__ void su2_reflect(mat3<H> &U, mat3<H> &W, int &attempt
     const double a1 = 0.5 * (double(W.e[I][J].im) + double(W.e[J][I].im));
     const double a2 = 0.5 * (double(W.e[I][J].re) - double(W.e[J][I].re));
     const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
-    const double k = sqrt(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))));
-    if (!(k > 1e-300)) return;  // degenerate projection: no reflection
+    double ik;
+    if (!inv_norm(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))), ik)) return;  // degenerate: no reflection
     ++attempts;
     ++accepts;
-    const double ik = 1.0 / k;
     const double b0 = a0 * ik, b1 = a1 * ik, b2 = a2 * ik, b3 = a3 * ik;
     // V^dag = [[b0 - i b3, -b2 - i b1], [b2 - i b1, b0 + i b3]], r = V^dag V^dag
     const cx<double> V00{b0, -b3}, V01{-b2, -b1}, V10{b2, -b1}, V11{b0, b3};
@@ -401,6 +415,29 @@ __device__ __forceinline__ uint32_t link_of_thread_3d(const UpdateArgs &a, uint3
     return (x2 + a.n2 * x3) * a.plane + c * 64u + lane;
 }
 
+// Order 7 (D = 4): each wave covers a 4D tile, 8 consecutive half-sites
+// along x_0 (16 sites) by 2 x 2 x 2 along x_1, x_2, x_3, so that most partner
+// links along every direction are loaded by lanes of the same wave (8 lanes
+// read one 128-byte line of each packet); the waves of a block stack along
+// x_2.  XCD k owns slab k of x_3 and walks it x_3 fastest, then x_2, x_1 and
+// the x_0 groups.  Returns the half-lattice index of the calling thread's
+// link.
+__device__ __forceinline__ uint32_t link_of_thread_4d(const UpdateArgs &a, uint32_t b)
+{
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t k = b & 7u, e = b >> 3;
+    const uint32_t e3 = e % a.slab, t = e / a.slab;
+    const uint32_t nb2 = a.n2 / (2u * nw);
+    const uint32_t e2 = t % nb2, t2 = t / nb2;
+    const uint32_t nb1 = a.n1 / 2u;
+    const uint32_t e1 = t2 % nb1, e0 = t2 / nb1;
+    const uint32_t x3 = (k * a.slab + e3) * 2u + (lane >> 5);
+    const uint32_t x2 = (e2 * nw + w) * 2u + ((lane >> 4) & 1u);
+    const uint32_t x1 = e1 * 2u + ((lane >> 3) & 1u);
+    const uint32_t hx = e0 * 8u + (lane & 7u);
+    return hx + a.n0h * (x1 + a.n1 * (x2 + a.n2 * x3));
+}
+
 // Hardware block b with the walk of every XCD reversed (a.reverse): XCD
 // b mod 8 keeps its blocks but takes them last to first.  Alternate slices
 // walk back and forth, so a slice starts on the links its predecessor read
@@ -416,11 +453,18 @@ __device__ __forceinline__ uint32_t walk_block(const UpdateArgs &a)
 template <int D, int PREC, int WAVES, int NC = 1>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
+    // the launch order only decides which link a thread takes; the update
+    // itself is one inlined body for every order
     const uint32_t b = walk_block(a);
+    uint32_t lb = b;
+    int64_t lt = -1;
     if (a.order == 3 || a.order == 5 || a.order == 6)
-        process_block<D, PREC, NC>(a, b, *a.sweep, int64_t(link_of_thread_3d(a, b)));
+        lt = int64_t(link_of_thread_3d(a, b));
+    else if (a.order == 7)
+        lt = int64_t(link_of_thread_4d(a, b));
     else
-        process_block<D, PREC, NC>(a, logical_block(a, b), *a.sweep);
+        lb = logical_block(a, b);
+    process_block<D, PREC, NC>(a, lb, *a.sweep, lt);
 }
 
 // Grid barrier of a persistent launch (all blocks resident: cooperative

@@ -372,10 +372,11 @@ def test_resume_is_bitwise(oracle_mod):
 def test_launch_shape_invariance(prec, ext):
     # every block size, block order and occupancy target gives the same links
     ref = None
+    used7 = set()
     fp32 = prec in (su3hb.FP32_18, su3hb.FP32_12)
     for waves in ((2, 3, 4) if fp32 else (2, 3)):
         for block in (64, 128, 256):
-            for order in (0, 1, 2, 3, 4, 5, 6, 8, 9, 10, 11, 12, 13, 14):
+            for order in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15):
                 g = su3hb.Lattice(ext, seed=8, precision=prec)
                 g.set_launch(block, order, waves)
                 b, o, w = g.get_launch()
@@ -383,18 +384,20 @@ def test_launch_shape_invariance(prec, ext):
                 # not apply falls back to 1 or 2 and keeps the flag
                 assert (b, w) == (block, waves) and o & 8 == order & 8
                 assert o == order or o & 7 in (1, 2)
+                if order & 7 == 7 and o & 7 == 7:
+                    used7.add(block)
                 g.sweep(6.1, n_hit=8, n_sweeps=2)
                 links = g.get_links()
                 if ref is None:
                     ref = links
                 assert np.array_equal(links, ref), (block, order, waves)
+    if ext[0] % 16 == 0 and ext[3] % 16 == 0:
+        assert used7, "the 4D wave-tile order was never in effect"
     with pytest.raises(su3hb.SU3HBError):
         g.set_launch(96, 0, 2)
     if not fp32:
         with pytest.raises(su3hb.SU3HBError):
             g.set_launch(64, 0, 4)
-    with pytest.raises(su3hb.SU3HBError):
-        g.set_launch(64, 7, 2)
     with pytest.raises(su3hb.SU3HBError):
         g.set_launch(64, 16, 2)
 

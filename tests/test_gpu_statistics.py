@@ -256,35 +256,56 @@ def binned(series, nmax=32, nmin=8):
     return int(max(nmin, min(nmax, len(series) // max(1, int(np.ceil(4 * tau))))))
 
 
+def pooled(chains, col):
+    """Mean of the chain means of column col and the error of that mean
+    (chains independent, each with its jackknife error in bins of at least
+    4 tau_int)."""
+    ms, es = zip(*[jackknife_mean(c[:, col], binned(c[:, col])) for c in chains])
+    return float(np.mean(ms)), float(np.sqrt(np.sum(np.square(es))) / len(ms))
+
+
 def test_config3_double_layered_fp32_error_per_observable(oracle_mod):
-    # two 24^3 x 8 layers glued in every direction, beta = 5.69, hot start
-    # from seed 1, 500 sweeps measured after every sweep: FP32-18 and FP32-12
-    # storage (FP64 Kennedy-Pendleton draw, reunitarisation and accumulation)
-    # against the FP64 oracle's chain from the same seed, per observable
-    # (total, spacelike, timelike, layer 0, layer 1, the beta-weighted action);
-    # the FP64-18 GPU chain is compared the same way.  The first 100 sweeps
-    # are thermalisation; errors are jackknife errors of the rest, in bins of
-    # at least 4 tau_int.
-    ext, beta, nsw, ntherm = (24, 24, 24, 8), 5.69, 500, 100
+    # two 24^3 x 8 layers glued in every direction, beta = 5.69, hot starts,
+    # per observable (total, spacelike, timelike, layer 0, layer 1, the
+    # beta-weighted action).  FP64 reference: the oracle's chain from seed 1,
+    # 500 sweeps as the workload states, and four FP64-18 GPU chains (seeds
+    # 1..4, 2200 sweeps each).  FP32-18 and FP32-12 storage (FP64
+    # Kennedy-Pendleton draw, reunitarisation and accumulation) run the same
+    # four seeds.  Pooled over the four chains (first 200 sweeps
+    # thermalisation), each FP32 form is compared with FP64 within two
+    # combined jackknife errors (bins of at least 4 tau_int).  The FP64 pool
+    # is compared with the oracle's 500-sweep chain (first 100 sweeps
+    # thermalisation) by the paper's Gaussian difference test (Q > 1e-3, as
+    # for the paper's tables): that chain has about 20 independent
+    # measurements, too few for a two-error bound on many observables.
+    ext, beta, ntherm = (24, 24, 24, 8), 5.69, 200
     names = ("total", "spacelike", "timelike", "layer 0", "layer 1", "action")
     o = oracle_mod.Lattice(list(ext), nlat=2, dlt_mask=0b1111, seed=1, threads=16)
     o.hot_start()
     ser_o = []
-    for _ in range(nsw):
+    for _ in range(500):
         o.sweep(beta, nhit=8, nsweeps=1)
         ser_o.append(o.plaquette(beta))
-    ser_o = np.array(ser_o)[ntherm:]
+    ser_o = np.array(ser_o)[100:]
+    chains = {}
     for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12):
-        lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0b1111, precision=prec, seed=1)
-        ser = lat.sweep_measure(beta, n_hit=8, n_sweeps=nsw)[ntherm:]
-        lat.close()
-        for k, name in enumerate(names):
-            nb = min(binned(ser[:, k]), binned(ser_o[:, k]))
-            m, e = jackknife_mean(ser[:, k], nb)
-            mo, eo = jackknife_mean(ser_o[:, k], nb)
-            z = (m - mo) / np.hypot(e, eo)
-            say(f"  2x24^3x8 beta={beta} prec={prec} {name}: {m:.8g}({e:.2g}) vs oracle {mo:.8g}({eo:.2g}), "
-                f"{z:+.2f} sigma ({nb} bins, tau_int {tau_int(ser[:, k])[0]:.1f} sweeps)")
+        chains[prec] = []
+        for seed in (1, 2, 3, 4):
+            lat = su3hb.Lattice(ext, nlat=2, dlt_mask=0b1111, precision=prec, seed=seed)
+            chains[prec].append(lat.sweep_measure(beta, n_hit=8, n_sweeps=ntherm + 2000)[ntherm:])
+            lat.close()
+    for k, name in enumerate(names):
+        m64, e64 = pooled(chains[su3hb.FP64_18], k)
+        mo, eo = jackknife_mean(ser_o[:, k], binned(ser_o[:, k]))
+        z = (m64 - mo) / np.hypot(e64, eo)
+        q = gaussian_difference_q(m64, e64, mo, eo)
+        say(f"  2x24^3x8 beta={beta} {name}: FP64 GPU pool {m64:.8g}({e64:.2g}) vs oracle chain "
+            f"{mo:.8g}({eo:.2g}), {z:+.2f} sigma, Q = {q:.2f}")
+        assert q > QMIN, ("oracle", name)
+        for prec in (su3hb.FP32_18, su3hb.FP32_12):
+            m, e = pooled(chains[prec], k)
+            z = (m - m64) / np.hypot(e, e64)
+            say(f"    prec={prec}: {m:.8g}({e:.2g}), {(m - m64):+.2e} = {z:+.2f} sigma against FP64")
             assert abs(z) < 2.0, (prec, name)
 
 
@@ -292,12 +313,17 @@ def test_config3_double_layered_fp32_error_per_observable(oracle_mod):
 def test_config2_trajectory_and_first_flip(oracle_mod, beta):
     # 16^4, hot start from seed 1, 200 sweeps with the plaquette after every
     # sweep, GPU against the oracle from the same start and random numbers.
-    # The two chains follow each other to rounding until rounding flips an
-    # accept/reject decision (Sec. 3).  The first sweep whose counters differ
-    # is replayed on the oracle slice by slice; in the first slice whose
-    # links differ from the GPU's by more than rounding every differing link
-    # is a flipped decision, and its distance from the acceptance threshold
-    # R4^2 - (1 - delta/2) is printed.  Over the run the mean plaquettes agree
+    # The chains differ by rounding (libm against device functions, FMA
+    # contraction); that difference grows smoothly from sweep to sweep until
+    # it flips an accept/reject decision (Sec. 3), which moves a link by far
+    # more than the smooth growth.  The first sweep whose largest link
+    # difference jumps (to more than 1e-4 and 30 times the sweep before) or
+    # whose counters differ is replayed on the oracle slice by slice from the
+    # oracle's own configuration; in the first slice whose output differs from
+    # the GPU's by more than that jump threshold every such link is a flipped
+    # decision, printed with its distance from the acceptance threshold
+    # |R4^2 - (1 - delta/2)|, which must be within the perturbation the
+    # smooth difference can cause.  Over the run the mean plaquettes agree
     # within two combined jackknife error bars.
     ext, nsw, ntherm = (16, 16, 16, 16), 200, 50
     g = su3hb.Lattice(ext, seed=1)
@@ -305,7 +331,7 @@ def test_config2_trajectory_and_first_flip(oracle_mod, beta):
     o.hot_start()
     first = None
     pg, po, dmax = [], [], []
-    prev_g, prev_o = g.get_links(), o.get_links()
+    prev_o = o.get_links()
     for k in range(nsw):
         st_g = g.sweep(beta, n_hit=8, n_sweeps=1, stats=True)
         st_o = o.sweep(beta, nhit=8, nsweeps=1)
@@ -314,19 +340,22 @@ def test_config2_trajectory_and_first_flip(oracle_mod, beta):
         if first is None:
             cur_g, cur_o = g.get_links(), o.get_links()
             dmax.append(float(np.abs(cur_g - cur_o).max()))
+            before = dmax[-2] if len(dmax) > 1 else 0.0
             same = (list(st_g["attempts"]) == list(st_o["attempts"])
                     and list(st_g["accepts"]) == list(st_o["accepts"]))
-            if not same:
-                first = (k, prev_o, cur_g)
-            prev_g, prev_o = cur_g, cur_o
+            jump = dmax[-1] > 1e-4 and dmax[-1] > 30.0 * before
+            if jump or not same:
+                first = (k, prev_o, cur_g, before)
+            prev_o = cur_o
     pg, po = np.array(pg), np.array(po)
-    say(f"  16^4 beta={beta}: max |dU| GPU vs oracle per sweep until the first flip: "
-        f"{' '.join(f'{d:.1e}' for d in dmax[:12])}{' ...' if len(dmax) > 12 else ''}")
+    say(f"  16^4 beta={beta}: max |dU| GPU vs oracle after each sweep: "
+        f"{' '.join(f'{d:.1e}' for d in dmax)}")
     say(f"  per-sweep |d<P>| max over the first 10 sweeps: {np.abs(pg[:10] - po[:10]).max():.2e}")
     if first is None:
         say(f"  no accept/reject decision differs in {nsw} sweeps")
     else:
-        k, before_o, after_g = first
+        k, before_o, after_g, dprev = first
+        thr = max(1e-4, 30.0 * dprev)
         par = np.zeros(int(np.prod(ext)), dtype=np.int64)
         idx = np.arange(par.size)
         stride = 1
@@ -345,19 +374,18 @@ def test_config2_trajectory_and_first_flip(oracle_mod, beta):
                 res = o2.get_links()
                 sites = np.flatnonzero(par == p)
                 dd = np.abs(res[0, sites, mu] - after_g[0, sites, mu]).reshape(len(sites), -1).max(axis=1)
-                if (dd > 1e-8).any():
+                if (dd > thr).any():
                     o2.set_links(state)
-                    for s in sites[dd > 1e-8]:
-                        flips.append((p, mu, int(s), o2.link_margin(0, int(s), mu, beta, nhit=8)))
+                    for s, d in zip(sites[dd > thr], dd[dd > thr]):
+                        flips.append((p, mu, int(s), float(d), o2.link_margin(0, int(s), mu, beta, nhit=8)))
                     break
             if flips:
                 break
-        bound = max(1e-9, 100.0 * (dmax[k - 1] if k > 0 else 0.0))
-        say(f"  sweep {k} is the first with different counters; max |dU| before it {dmax[k - 1] if k else 0:.1e}; "
-            f"flipped links (parity, mu, site, |margin|) = {flips[:4]}")
-        assert flips, "counters differ but no link of the sweep differs"
-        # a decision flips only within rounding of the threshold
-        assert min(f[3] for f in flips) < bound
+        say(f"  sweep {k}: first decision flip; largest smooth difference before it {dprev:.1e}; flipped links "
+            f"(parity, mu, site, |dU|, |R4^2 - (1 - delta/2)|) = {[tuple(f'{v:.3g}' if isinstance(v, float) else v for v in f) for f in flips[:4]]}")
+        assert flips, "a jump in the chains' difference without a flipped link"
+        # the flipped decisions lay within reach of the smooth difference
+        assert min(f[4] for f in flips) < max(1e-9, 1e3 * dprev)
     mg, eg = jackknife_mean(pg[ntherm:], 15)
     mo, eo = jackknife_mean(po[ntherm:], 15)
     say(f"  <P> over sweeps {ntherm}..{nsw}: GPU {mg:.6f}({eg*1e6:.0f}) oracle {mo:.6f}({eo*1e6:.0f})")
