@@ -555,40 +555,21 @@ __device__ __forceinline__ void store_link(const LinkRef &r, const mat3<double> 
     }
 }
 
-// The FP64 matrix a link reads back as after store_link<PREC>(m): rounded to
-// the storage precision, with row 2 rebuilt for 12-real storage.
+// The matrix a link reads back as after store_link<PREC>(m), in the storage
+// precision: rounded, with row 2 rebuilt for 12-real storage.
 template <int PREC>
-__device__ __forceinline__ mat3<double> stored_form(const mat3<double> &m)
+__device__ __forceinline__ mat3<typename Store<PREC>::real> stored_form_r(const mat3<double> &m)
 {
     using R = typename Store<PREC>::real;
-    if constexpr (Store<PREC>::NE == 9 && sizeof(R) == sizeof(double)) {
-        return m;
-    } else {
-        mat3<R> r;
+    mat3<R> r;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) r.e[i][j] = cx<R>{R(m.e[i][j].re), R(m.e[i][j].im)};
-        if constexpr (Store<PREC>::NE == 6) third_row(r);
-        return widen<double>(r);
-    }
+        for (int j = 0; j < 3; ++j) r.e[i][j] = cx<R>{R(m.e[i][j].re), R(m.e[i][j].im)};
+    if constexpr (Store<PREC>::NE == 6) third_row(r);
+    return r;
 }
 
-// Both staples of one plane (nu, mu) at x:
-//   forward  U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag        = F1 (F3 F2)^dag
-//   backward U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)   = (B2 B1)^dag B3
-// acc += wf F1 T + wb S B3 with T = (F3 F2)^dag and S = (B2 B1)^dag.  The
-// loads come in pairs that other threads of the slice read too (F3 of the
-// link at x is B1 of the link at x - mu + nu, F2 of x is B2 of x + 2 nu, F1
-// of x is B3 of x + mu + nu), each pair issued back to back so that the
-// second read of a line finds it still in L2.  Every neighbour is loaded as
-// a whole link: with tiled storage that is one contiguous stretch per wave.
-//
-// CLASSES (a measured plane of a two-layer lattice): acc receives exactly the
-// same operations, and the unweighted forward term F1 (F3 F2)^dag and
-// backward term (B2 B1)^dag B3 are also added to the measurement classes cf
-// and cb, held in LDS as cls[(c * 9 + e) * stride + t] (slot t of class c,
-// element e).
 // Rows 0 and 1 of a link as stored by 12-real storage (row 2 left unset).
 template <int PREC>
 __device__ __forceinline__ mat3<typename Store<PREC>::real> load_rows01(const LinkRef &r)

@@ -56,17 +56,18 @@ __device__ __forceinline__ void rotate_rows(mat3<H> &U, mat3<H> &W, const cx<H> 
 
 // One SU(2)-subgroup heatbath on rows (I, J) of U (and W = U A), with U, W
 // and the rotation in H (double for FP64 storage, float for FP32 storage).
-// The norm k, alpha and the Kennedy-Pendleton draw and acceptance test are
-// FP64 in every mode.
+// The quaternion components of the block are formed in H (the precision W
+// is held in) and widened; the norm k, alpha and the Kennedy-Pendleton draw
+// and acceptance test are FP64 in every mode.
 template <typename H, int I, int J, int SUB>
 __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t lid, uint32_t sweep, int nhit,
                                              uint32_t k0, uint32_t k1, int &attempts, int &accepts)
 {
     // quaternion part a0 + i a.sigma of the 2x2 block (I, J) of W
-    const double a0 = 0.5 * (double(W.e[I][I].re) + double(W.e[J][J].re));
-    const double a1 = 0.5 * (double(W.e[I][J].im) + double(W.e[J][I].im));
-    const double a2 = 0.5 * (double(W.e[I][J].re) - double(W.e[J][I].re));
-    const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
+    const double a0 = double(H(0.5) * (W.e[I][I].re + W.e[J][J].re));
+    const double a1 = double(H(0.5) * (W.e[I][J].im + W.e[J][I].im));
+    const double a2 = double(H(0.5) * (W.e[I][J].re - W.e[J][I].re));
+    const double a3 = double(H(0.5) * (W.e[I][I].im - W.e[J][J].im));
     // alpha = 2k/3; the draw multiplies by 1/alpha = 1.5/k, computed once
     double ik;
     if (!inv_norm(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))), ik)) return;  // degenerate: every hit rejected
@@ -126,10 +127,10 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
 template <typename H, int I, int J>
 __device__ __forceinline__ void su2_reflect(mat3<H> &U, mat3<H> &W, int &attempts, int &accepts)
 {
-    const double a0 = 0.5 * (double(W.e[I][I].re) + double(W.e[J][J].re));
-    const double a1 = 0.5 * (double(W.e[I][J].im) + double(W.e[J][I].im));
-    const double a2 = 0.5 * (double(W.e[I][J].re) - double(W.e[J][I].re));
-    const double a3 = 0.5 * (double(W.e[I][I].im) - double(W.e[J][J].im));
+    const double a0 = double(H(0.5) * (W.e[I][I].re + W.e[J][J].re));
+    const double a1 = double(H(0.5) * (W.e[I][J].im + W.e[J][I].im));
+    const double a2 = double(H(0.5) * (W.e[I][J].re - W.e[J][I].re));
+    const double a3 = double(H(0.5) * (W.e[I][I].im - W.e[J][J].im));
     double ik;
     if (!inv_norm(fma(a0, a0, fma(a1, a1, fma(a2, a2, a3 * a3))), ik)) return;  // degenerate: no reflection
     ++attempts;
@@ -271,13 +272,15 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
     mat3<double> Ud = widen<double>(U);
     reunitarize(Ud);
     if (measure) {
-        const mat3<double> Us = stored_form<PREC>(Ud);
+        // the link as it will be read back, times the snapshot staple: each
+        // link's trace in the storage precision, the sums in FP64
+        const mat3<R> Us = stored_form_r<PREC>(Ud);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             mat3<R> M;
 #pragma unroll
             for (int e = 0; e < 9; ++e) M.e[e / 3][e % 3] = alow[(c * 9 + e) * bd + tid];
-            plaq[c] += re_tr_nn(Us, widen<double>(M)) * (1.0 / 3.0);
+            plaq[c] += double(re_tr_nn(Us, M)) * (1.0 / 3.0);
         }
     }
     store_link<PREC>(uptr, Ud);
