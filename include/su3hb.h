@@ -198,9 +198,16 @@ int su3hb_set_state(su3hb_lattice *lat, uint64_t seed, uint64_t sweep);
  * that does is used (4 and 2 fall back to 1; 3, 5 and 6 to 2 or 1; 7 to 1).
  * Adding 8 to an order makes every second slice of a sweep walk each XCD's
  * blocks last to first, so a slice starts on the links the slice before it
- * read last.  waves: minimum waves per SIMD the kernel is compiled for: 2;
+ * read last.  Adding 16 makes every wave copy the U_mu links that the
+ * staples of its planes nu = 0, 1 read (Sec. 2.1, the staple sum) into LDS
+ * once, n_0/2 half-sites on either side of its own 64, and read them from
+ * there (single-layer lattices outside batches, orders 0 to 6; ignored
+ * elsewhere).  waves: minimum waves per SIMD the kernel is compiled for: 2;
  * 3 for D = 4; 4 for D = 4 with FP32 links.  Results are bit-identical for
- * every shape.  get_launch reports the order in effect (with the 8). */
+ * every shape.  get_launch reports the order in effect (with the 8 and 16).
+ * A shape whose LDS (staple snapshots of a measured slice plus staging
+ * areas) exceeds the device's per-block limit returns SU3HB_EUNSUPPORTED
+ * and leaves the launch shape as it was. */
 int su3hb_set_launch(su3hb_lattice *lat, int block, int order, int waves);
 int su3hb_get_launch(const su3hb_lattice *lat, int *block, int *order, int *waves);
 

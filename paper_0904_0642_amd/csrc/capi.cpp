@@ -326,18 +326,30 @@ bool tile4_order_ok(const su3hb_lattice *L, int block)
 
 // Flag added to an order: alternate slices walk every XCD's blocks backwards.
 constexpr int kOrderReverse = 8;
+// Flag added to an order: every wave stages the U_mu links that its planes
+// nu = 0, 1 read in LDS (single-layer lattices outside batches, orders 0 to
+// 6, which give each wave 64 consecutive half-lattice indices).
+constexpr int kOrderStage = 16;
 
-// Block order in effect, without the reverse flag.
+// Block order in effect, without the flags.
 int base_order(const su3hb_lattice *L)
 {
-    const int o = L->order & ~kOrderReverse;
+    const int o = L->order & ~(kOrderReverse | kOrderStage);
     if (o == 7 && !tile4_order_ok(L, L->block)) return 1;
     if (is_cube_order(o) && !cube_order_ok(L, L->block, o)) return slab_order_ok(L, L->block) ? 2 : 1;
     if ((o == 2 || o == 4) && !slab_order_ok(L, L->block)) return 1;
     return o;
 }
 
-int effective_order(const su3hb_lattice *L) { return base_order(L) | (L->order & kOrderReverse); }
+bool stage_applies(const su3hb_lattice *L)
+{
+    return (L->order & kOrderStage) && !L->batch && L->nrep == 1 && L->reps[0].nlat == 1 && base_order(L) != 7;
+}
+
+int effective_order(const su3hb_lattice *L)
+{
+    return base_order(L) | (L->order & kOrderReverse) | (stage_applies(L) ? kOrderStage : 0);
+}
 
 UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
 {
@@ -368,6 +380,10 @@ UpdateArgs update_args(const su3hb_lattice *L, double b0, double b1, int nhit)
             a.slab = nl / (8u * a.tile3);
             a.cp = a.plane / 64u;
         }
+    }
+    if (stage_applies(L)) {
+        a.stage = 1;
+        a.stage_r = uint32_t(L->reps[0].n[0]) / 2u;
     }
     a.beta0 = b0;
     a.beta1 = b1;
@@ -682,16 +698,37 @@ int apply_launch(su3hb_lattice *L, int block, int order, int waves)
 {
     if (block != 64 && block != 128 && block != 256)
         return fail(SU3HB_EINVAL, "block = %d, expected 64, 128 or 256", block);
-    if (order < 0 || (order & ~kOrderReverse) > 7)
-        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 7, optionally + %d", order, kOrderReverse);
+    if (order < 0 || (order & ~(kOrderReverse | kOrderStage)) > 7)
+        return fail(SU3HB_EINVAL, "order = %d, expected 0 .. 7, optionally + %d and + %d", order, kOrderReverse,
+                    kOrderStage);
     if (waves != 2 && !(waves == 3 && L->nd == 4) && !(waves == 4 && L->nd == 4 && is_fp32(L->prec)))
         return fail(SU3HB_EINVAL, "waves = %d: 2, or 3 for D = 4, or 4 for D = 4 with FP32 links", waves);
     HIPCHK(hipStreamSynchronize(L->stream));
     drop_graph(L);
+    const int old_block = L->block, old_order = L->order, old_waves = L->waves;
     L->block = block;
     L->order = order;
     L->waves = waves;
     layout_reps(L);
+    // a measured parity-1 slice asks for the most LDS: staple snapshots and,
+    // when staging, the staging areas
+    size_t need = 0, limit = 0;
+    UpdateArgs m = update_args(L, 6.0, 6.0, 8);
+    m.parity = 1;
+    if (fused_measure(L)) {
+        m.meas = reinterpret_cast<double *>(uintptr_t(256));  // only tested for null
+        m.meas_classes = meas_classes(L);
+    }
+    const hipError_t e = update_lds(L->nd, L->prec, L->waves, dim3(block), m, &need, &limit);
+    if (e != hipSuccess || limit == 0 || need > limit) {
+        L->block = old_block;
+        L->order = old_order;
+        L->waves = old_waves;
+        layout_reps(L);
+        if (e != hipSuccess) return fail(SU3HB_EHIP, "LDS query: %s", hipGetErrorString(e));
+        return fail(SU3HB_EUNSUPPORTED, "launch (%d, %d, %d) needs %zu bytes of LDS per block, the device allows %zu",
+                    block, order, waves, need, limit);
+    }
     return upload_reps(L);
 }
 
@@ -975,6 +1012,10 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
                 if (is_cube_order(order) && (block == 64 || !cube_order_ok(L, block, order))) continue;
                 cands.push_back(Shape{block, order, waves});
                 cands.push_back(Shape{block, order | kOrderReverse, waves});
+                if (order != 7 && !L->batch && L->reps[0].nlat == 1) {
+                    cands.push_back(Shape{block, order | kOrderStage, waves});
+                    cands.push_back(Shape{block, order | kOrderReverse | kOrderStage, waves});
+                }
             }
     }
     const double b = L->batch ? 0.0 : 6.0;
@@ -991,6 +1032,10 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     for (int pass = 0; pass < 2 && !rc; ++pass)
         for (size_t i = 0; i < cands.size() && !rc; ++i) {
             rc = apply_launch(L, cands[i].block, cands[i].order, cands[i].waves);
+            if (rc == SU3HB_EUNSUPPORTED) {  // its LDS does not fit: not a candidate
+                rc = SU3HB_OK;
+                continue;
+            }
             if (rc) break;
             rc = enqueue_sweep(L, L->stream, b, b, 8, 0);  // warm-up
             if (rc) break;

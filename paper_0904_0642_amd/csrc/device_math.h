@@ -502,10 +502,11 @@ __device__ __forceinline__ cx<typename Store<PREC>::real> load_elem(const LinkRe
     }
 }
 
-// A whole link; NT: the non-temporal policy, for a link no other thread of
-// the launch reads.
+// The NE stored elements of a link (row 2 of 12-real storage left unset);
+// NT: the non-temporal policy, for a link no other thread of the launch
+// reads.
 template <int PREC, bool NT = false>
-__device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const LinkRef &r)
+__device__ __forceinline__ mat3<typename Store<PREC>::real> load_stored(const LinkRef &r)
 {
     using R = typename Store<PREC>::real;
     constexpr int NE = Store<PREC>::NE;
@@ -523,7 +524,15 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const Link
         }
         if constexpr (NE & 1) m.e[2][2] = load_elem<PREC, NT>(r, NE - 1);
     }
-    if constexpr (NE == 6) third_row(m);
+    return m;
+}
+
+// A whole link.
+template <int PREC, bool NT = false>
+__device__ __forceinline__ mat3<typename Store<PREC>::real> load_link(const LinkRef &r)
+{
+    mat3<typename Store<PREC>::real> m = load_stored<PREC, NT>(r);
+    if constexpr (Store<PREC>::NE == 6) third_row(m);
     return m;
 }
 
@@ -586,6 +595,57 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> load_rows01(const Li
     return m;
 }
 
+// A neighbour link read from global memory or from a wave's staging area in
+// LDS.  The staging area holds the stored elements of nslot consecutive
+// links of one slab, element-major (element e of slot i at e * nslot + i);
+// the link is taken from there when stg is set and slot < nslot, else from
+// global memory.  Both give the same bits.
+template <int PREC>
+struct LinkSrc {
+    LinkRef ref;
+    const cx<typename Store<PREC>::real> *stg;
+    uint32_t slot, nslot;
+};
+
+template <int PREC>
+__device__ __forceinline__ LinkSrc<PREC> from_global(const LinkRef &r)
+{
+    return LinkSrc<PREC>{r, nullptr, 0u, 0u};
+}
+
+template <int PREC>
+__device__ __forceinline__ bool staged(const LinkSrc<PREC> &s)
+{
+    return s.stg != nullptr && s.slot < s.nslot;
+}
+
+template <int PREC>
+__device__ __forceinline__ mat3<typename Store<PREC>::real> stored_from_lds(const LinkSrc<PREC> &s)
+{
+    mat3<typename Store<PREC>::real> m;
+#pragma unroll
+    for (int e = 0; e < Store<PREC>::NE; ++e) m.e[e / 3][e % 3] = s.stg[e * s.nslot + s.slot];
+    return m;
+}
+
+template <int PREC>
+__device__ __forceinline__ mat3<typename Store<PREC>::real> fetch_link(const LinkSrc<PREC> &s)
+{
+    if (staged(s)) {
+        mat3<typename Store<PREC>::real> m = stored_from_lds(s);
+        if constexpr (Store<PREC>::NE == 6) third_row(m);
+        return m;
+    }
+    return load_link<PREC>(s.ref);
+}
+
+template <int PREC>
+__device__ __forceinline__ mat3<typename Store<PREC>::real> fetch_rows01(const LinkSrc<PREC> &s)
+{
+    if (staged(s)) return stored_from_lds(s);
+    return load_rows01<PREC>(s.ref);
+}
+
 // Both staples of one plane for FP32 12-real storage.  Every product of
 // SU(3) matrices is in SU(3), so only its rows 0 and 1 are multiplied out
 // and row 2 is conj(row0 x row1); then F3, F1 and B2 are needed only as
@@ -598,8 +658,8 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> load_rows01(const Li
 // form below.  CLASSES as there, with Q and R as the unweighted terms.
 template <int PREC, bool CLASSES>
 __device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
-                                                     const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
-                                                     const LinkRef &b2, const LinkRef &b3,
+                                                     const LinkSrc<PREC> &f2, const LinkRef &f3, const LinkRef &b1,
+                                                     const LinkSrc<PREC> &b2, const LinkRef &b3,
                                                      typename Store<PREC>::real wf, typename Store<PREC>::real wb,
                                                      cx<typename Store<PREC>::real> *cls, uint32_t stride,
                                                      uint32_t t, int cf, int cb)
@@ -609,7 +669,7 @@ __device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::
     const mat3<R> mb1 = load_link<PREC>(b1);
     mat3<R> M;
     {
-        const mat3<R> m2 = load_link<PREC>(f2);
+        const mat3<R> m2 = fetch_link<PREC>(f2);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -623,7 +683,7 @@ __device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::
     }
     mat3<R> N;
     {
-        const mat3<R> mb2 = load_rows01<PREC>(b2);
+        const mat3<R> mb2 = fetch_rows01<PREC>(b2);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -675,8 +735,8 @@ __device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::
 
 template <int PREC, bool CLASSES = false>
 __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
-                                                  const LinkRef &f2, const LinkRef &f3, const LinkRef &b1,
-                                                  const LinkRef &b2, const LinkRef &b3,
+                                                  const LinkSrc<PREC> &f2, const LinkRef &f3, const LinkRef &b1,
+                                                  const LinkSrc<PREC> &b2, const LinkRef &b3,
                                                   typename Store<PREC>::real wf, typename Store<PREC>::real wb,
                                                   cx<typename Store<PREC>::real> *cls = nullptr,
                                                   uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
@@ -692,7 +752,7 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
     mat3<R> T, Tu;
     set_zero(T);
     {
-        const mat3<R> m2 = load_link<PREC>(f2);
+        const mat3<R> m2 = fetch_link<PREC>(f2);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -708,7 +768,7 @@ __device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::rea
     // S_ij = wb conj(sum_k B2_jk B1_ki): row j of B2 gives column j of S
     mat3<R> S, Su;
     {
-        const mat3<R> mb2 = load_link<PREC>(b2);
+        const mat3<R> mb2 = fetch_link<PREC>(b2);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll

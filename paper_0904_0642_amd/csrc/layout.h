@@ -87,6 +87,8 @@ struct UpdateArgs {
     uint32_t plane;              // order 3: half-sites of one (x_{D-2}, x_{D-1}) plane
     uint32_t tile2, tile3;       // order 3: waves of a block along x_{D-2} and x_{D-1}
     uint32_t n0h, n1;            // order 7: n_0 / 2 and n_1
+    int stage;                   // 1: each wave stages the U_mu links its planes nu = 0, 1 read in LDS
+    uint32_t stage_r;            // staging halo: n_0 / 2 half-sites before and after a wave's 64
     double beta0, beta1;
     const uint32_t *sweep;       // device sweep counter
     StatSlot *stats;             // kStatSlots slots

@@ -168,7 +168,8 @@ __device__ __forceinline__ void su2_reflect(mat3<H> &U, mat3<H> &W, int &attempt
 template <int D, int PREC, int NC>
 __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &rep, uint32_t lt,
                                             uint32_t sweep, int att[3], int acc[3], double &dtrace,
-                                            double *plaq)
+                                            double *plaq, const cx<typename Store<PREC>::real> *stg,
+                                            int32_t stg_lo)
 {
     using R = typename Store<PREC>::real;
     const int p = a.parity, q = 1 - a.parity, mu = a.mu;
@@ -223,15 +224,26 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
 
         const uint32_t tags_f = layer + l_pm + l_pn + layer;
         const uint32_t tags_b = l_mn + l_pmmn + layer + l_mn;
+        // U_mu(x + nu) and U_mu(x - nu): from the wave's staging area for
+        // nu = 0, 1 when the launch stages (single-layer lattices only)
+        LinkSrc<PREC> f2 = from_global<PREC>(link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn));
+        LinkSrc<PREC> b2 = from_global<PREC>(link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn));
+        if (nu < 2 && stg != nullptr) {
+            const uint32_t nslot = 64u + 2u * a.stage_r;
+            f2.stg = stg;
+            f2.slot = uint32_t(int32_t(s_pn >> 1) - stg_lo);
+            f2.nslot = nslot;
+            b2.stg = stg;
+            b2.slot = uint32_t(int32_t(s_mn >> 1) - stg_lo);
+            b2.nslot = nslot;
+        }
         if constexpr (NC == 3) {
             if (measure && nu < mu) {
                 const int cf = layer == 0 ? (tags_f == 0 ? 0 : 1) : 2;
                 const int cb = l_mn == 0 ? (tags_b == 0 ? 0 : 1) : 2;
-                acc_plane_staples<PREC, true>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm),
-                                              link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn),
+                acc_plane_staples<PREC, true>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), f2,
                                               link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
-                                              link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn),
-                                              link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn),
+                                              link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), b2,
                                               link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn),
                                               single ? R(1) : R(tags_f == 0 ? beta0 : beta1),
                                               single ? R(1) : R(tags_b == 0 ? beta0 : beta1), alow, bd, tid,
@@ -239,11 +251,9 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
                 continue;
             }
         }
-        acc_plane_staples<PREC>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm),
-                                link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn),
+        acc_plane_staples<PREC>(A, link_ref<D, PREC>(a.links, rep, l_pm, nu, q, s_pm), f2,
                                 link_ref<D, PREC>(a.links, rep, layer, nu, p, x.s),
-                                link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn),
-                                link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn),
+                                link_ref<D, PREC>(a.links, rep, l_pmmn, nu, p, s_pmmn), b2,
                                 link_ref<D, PREC>(a.links, rep, l_mn, nu, q, s_mn),
                                 single ? R(1) : R(tags_f == 0 ? beta0 : beta1),
                                 single ? R(1) : R(tags_b == 0 ? beta0 : beta1));
@@ -340,6 +350,47 @@ __device__ __forceinline__ void flush_stats(const UpdateArgs &a, uint32_t lb, in
 // Update the links of logical block lb (replica found by binary search),
 // adding to the thread's counters; lt_override >= 0 gives the thread's link
 // directly (order 3).
+// Staging of the U_mu neighbours along directions 0 and 1 (launches with
+// a.stage, single-layer lattices, launch orders that give every wave 64
+// consecutive half-lattice indices hw .. hw + 63).  A step along direction
+// 0 moves h by at most n_0/2 - 1 (the wrap stays in the row), one along
+// direction 1 by exactly n_0/2 unless it wraps, so the parity-q U_mu links
+// that the wave's planes nu = 0, 1 read lie in h = hw - R .. hw + 63 + R,
+// R = n_0/2, except after a wrap along direction 1.  Every lane of the wave
+// (also lanes past the end of the lattice) copies its share of that range
+// into the wave's staging area once; the staple then reads those links from
+// LDS and the few outside the range from global memory.  The slice does not
+// write these links (it writes parity p), so both give the same values.
+// Returns the wave's staging area; stg_lo = hw - R.
+template <int D, int PREC>
+__device__ __forceinline__ const cx<typename Store<PREC>::real> *stage_wave(const UpdateArgs &a, const RepDesc &rep,
+                                                                           uint32_t lt, int32_t &stg_lo)
+{
+    using R = typename Store<PREC>::real;
+    constexpr int NE = Store<PREC>::NE;
+    extern __shared__ char s_dyn[];
+    const uint32_t lane = threadIdx.x & 63u, nslot = 64u + 2u * a.stage_r;
+    // the staging areas follow the staple snapshots of a measuring launch
+    const uint32_t snap = (a.meas != nullptr && a.parity == 1) ? blockDim.x * 9u * uint32_t(a.meas_classes) : 0u;
+    cx<R> *stg = reinterpret_cast<cx<R> *>(s_dyn) + snap + size_t(threadIdx.x >> 6) * nslot * NE;
+    stg_lo = int32_t(lt - lane) - int32_t(a.stage_r);
+    const int q = 1 - a.parity;
+    for (uint32_t slot = lane; slot < nslot; slot += 64u) {
+        const int32_t h = stg_lo + int32_t(slot);
+        if (h >= 0 && uint32_t(h) < rep.Vh) {
+            const mat3<R> m = load_stored<PREC>(link_ref<D, PREC>(a.links, rep, 0u, a.mu, q, 2u * uint32_t(h)));
+#pragma unroll
+            for (int e = 0; e < NE; ++e) stg[e * nslot + slot] = m.e[e / 3][e % 3];
+        }
+    }
+    // the wave's LDS operations complete in order: after the stores, any lane
+    // of the wave reads what the others wrote
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return stg;
+}
+
 template <int D, int PREC, int NC>
 __device__ __forceinline__ void block_links(const UpdateArgs &a, uint32_t lb, uint32_t sweep, int att[3], int acc[3],
                                             int &upd, double &dtrace, double *plaq, int64_t lt_override = -1)
@@ -350,8 +401,13 @@ __device__ __forceinline__ void block_links(const UpdateArgs &a, uint32_t lb, ui
         const RepDesc &rep = a.reps[r];
         const uint32_t lt = lt_override >= 0 ? uint32_t(lt_override)
                                              : (lb - first_block(rep, kind)) * blockDim.x + threadIdx.x;
+        const cx<typename Store<PREC>::real> *stg = nullptr;
+        int32_t stg_lo = 0;
+        if constexpr (NC == 1) {
+            if (a.stage) stg = stage_wave<D, PREC>(a, rep, lt, stg_lo);
+        }
         if (lt < rep.nlat * rep.Vh) {
-            update_link<D, PREC, NC>(a, rep, lt, sweep, att, acc, dtrace, plaq);
+            update_link<D, PREC, NC>(a, rep, lt, sweep, att, acc, dtrace, plaq, stg, stg_lo);
             ++upd;
         }
     }
@@ -554,7 +610,10 @@ template <int PREC>
 static size_t update_lds_bytes(dim3 block, const UpdateArgs &a)
 {
     using R = typename Store<PREC>::real;
-    return (a.meas != nullptr && a.parity == 1) ? size_t(block.x) * 9 * a.meas_classes * sizeof(cx<R>) : 0;
+    const size_t snap = (a.meas != nullptr && a.parity == 1) ? size_t(block.x) * 9 * a.meas_classes * sizeof(cx<R>) : 0;
+    if (!a.stage) return snap;
+    // the staging areas follow the snapshots
+    return snap + size_t(block.x / 64u) * (64u + 2u * a.stage_r) * Store<PREC>::NE * sizeof(cx<R>);
 }
 
 // The kernel a slice launch uses: the class-splitting form for measured

@@ -376,21 +376,26 @@ def test_launch_shape_invariance(prec, ext):
     fp32 = prec in (su3hb.FP32_18, su3hb.FP32_12)
     for waves in ((2, 3, 4) if fp32 else (2, 3)):
         for block in (64, 128, 256):
-            for order in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15):
+            for order in range(32):
                 g = su3hb.Lattice(ext, seed=8, precision=prec)
                 g.set_launch(block, order, waves)
                 b, o, w = g.get_launch()
-                # + 8: alternate slices walk backwards; an order that does
-                # not apply falls back to 1 or 2 and keeps the flag
+                # + 8: alternate slices walk backwards; + 16: waves stage
+                # U_mu neighbours in LDS (not with order 7); an order that
+                # does not apply falls back to 1 or 2 and keeps the flags
                 assert (b, w) == (block, waves) and o & 8 == order & 8
-                assert o == order or o & 7 in (1, 2)
+                assert o & 16 == (order & 16 if o & 7 != 7 else 0)
+                assert o & 7 == order & 7 or o & 7 in (1, 2)
                 if order & 7 == 7 and o & 7 == 7:
                     used7.add(block)
-                g.sweep(6.1, n_hit=8, n_sweeps=2)
+                series = g.sweep_measure(6.1, n_hit=8, n_sweeps=2)
                 links = g.get_links()
                 if ref is None:
-                    ref = links
+                    ref, ref_series = links, series
                 assert np.array_equal(links, ref), (block, order, waves)
+                # the fused measurement sums per block: other block sizes
+                # group the sum differently
+                assert np.allclose(series, ref_series, rtol=1e-12, atol=0, equal_nan=True), (block, order, waves)
     if ext[0] % 16 == 0 and ext[3] % 16 == 0:
         assert used7, "the 4D wave-tile order was never in effect"
     with pytest.raises(su3hb.SU3HBError):
@@ -399,7 +404,38 @@ def test_launch_shape_invariance(prec, ext):
         with pytest.raises(su3hb.SU3HBError):
             g.set_launch(64, 0, 4)
     with pytest.raises(su3hb.SU3HBError):
-        g.set_launch(64, 16, 2)
+        g.set_launch(64, 32, 2)
+
+
+@pytest.mark.parametrize("prec,ext", [(su3hb.FP64_18, [48, 8, 4, 4]), (su3hb.FP32_12, [48, 8, 4, 4]),
+                                      (su3hb.FP32_18, [10, 6, 4, 2]), (su3hb.FP64_12, [6, 10, 4, 2]),
+                                      (su3hb.FP64_18, [14, 6, 4]), (su3hb.FP32_12, [26, 22]),
+                                      (su3hb.FP64_18, [6, 4, 4, 2, 4])])
+def test_staged_neighbours_bit_identical(prec, ext):
+    # waves that stage the U_mu links of the planes nu = 0, 1 in LDS give the
+    # links, counters and fused plaquettes of the unstaged launch, also with
+    # ragged last waves, row wraps inside a wave and wraps along direction 1
+    ref = su3hb.Lattice(ext, seed=12, precision=prec)
+    ref.set_launch(128, 1, 2)
+    ref_series, ref_stats = ref.sweep_measure(5.9, n_hit=8, n_sweeps=3, stats=True)
+    staged = 0
+    for block in (64, 128, 256):
+        for order in (16, 17, 25, 18, 21, 22):
+            g = su3hb.Lattice(ext, seed=12, precision=prec)
+            g.set_launch(block, order, 2)
+            if not g.get_launch()[1] & 16:
+                continue
+            staged += 1
+            series, stats = g.sweep_measure(5.9, n_hit=8, n_sweeps=3, stats=True)
+            assert np.array_equal(g.get_links(), ref.get_links()), (block, order)
+            if block == 128 and order & 7 in (0, 1, 2, 4):  # the same links per block
+                assert np.array_equal(series, ref_series, equal_nan=True), (block, order)
+            assert np.allclose(series, ref_series, rtol=1e-12, atol=0, equal_nan=True), (block, order)
+            # counters exact; the running action change is a per-block sum
+            assert {k: v for k, v in stats.items() if k != "dtrace"} == \
+                {k: v for k, v in ref_stats.items() if k != "dtrace"}, (block, order)
+            assert stats["dtrace"] == pytest.approx(ref_stats["dtrace"], rel=1e-12, abs=1e-9)
+    assert staged >= 6
 
 
 def test_graph_replay_equals_direct_launches():
