@@ -1019,6 +1019,11 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
             }
     }
     const double b = L->batch ? 0.0 : 6.0;
+    // single lattices are timed with the fused measurement (its parity-1
+    // slices hold the staple snapshots in LDS, which decides the occupancy
+    // of some shapes); the series cursor is reset before every timed batch of
+    // at most 64 sweeps and after the tuning
+    const int meas = fused_measure(L) ? 1 : 0;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1037,13 +1042,16 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
                 continue;
             }
             if (rc) break;
-            rc = enqueue_sweep(L, L->stream, b, b, 8, 0);  // warm-up
+            if (meas && (rc = ensure_meas(L)) != SU3HB_OK) break;
+            if (hipSuccess != launch_counter_set(L->stream, L->d_cursor, 0)) { rc = fail(SU3HB_EHIP, "cursor"); break; }
+            rc = enqueue_sweep(L, L->stream, b, b, 8, meas);  // warm-up
             if (rc) break;
             int reps = 1;
             float ms = 0.f;
             for (;;) {
+                if (hipSuccess != launch_counter_set(L->stream, L->d_cursor, 0)) { rc = fail(SU3HB_EHIP, "cursor"); break; }
                 if (hipEventRecord(e0, L->stream) != hipSuccess) { rc = fail(SU3HB_EHIP, "event"); break; }
-                for (int k = 0; k < reps && !rc; ++k) rc = enqueue_sweep(L, L->stream, b, b, 8, 0);
+                for (int k = 0; k < reps && !rc; ++k) rc = enqueue_sweep(L, L->stream, b, b, 8, meas);
                 if (rc) break;
                 if (hipEventRecord(e1, L->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     rc = fail(SU3HB_EHIP, "event");
@@ -1062,6 +1070,7 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     hipEventDestroy(e1);
     HIPCHK(hipMemcpyAsync(L->links, backup, L->links_bytes, hipMemcpyDeviceToDevice, L->stream));
     HIPCHK(launch_counter_set(L->stream, L->d_sweep, uint32_t(sweep0)));
+    HIPCHK(launch_counter_set(L->stream, L->d_cursor, 0));
     HIPCHK(launch_stats_zero(L->stream, L->d_stats));
     HIPCHK(hipStreamSynchronize(L->stream));
     L->sweep = sweep0;

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "layout.h"
+#include "log_table.h"
 
 namespace su3hb {
 
@@ -267,44 +268,47 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// 32-bit word -> uniform double (r + 1) / 2^32 in (0, 1]
-__host__ __device__ __forceinline__ double u01(uint32_t r) { return (double(r) + 1.0) * 0x1p-32; }
+// 32-bit word -> uniform double (r + 1) / 2^32 in (0, 1], exact (one FMA)
+__host__ __device__ __forceinline__ double u01(uint32_t r) { return fma(double(r), 0x1p-32, 0x1p-32); }
 
 // ---------------------------------------------------------------------------
 // Elementary functions of a uniform u in (0, 1] (a Philox word (r+1)/2^32,
 // so u has at most 32 significant bits), written for this range only: a
 // few FP64 operations instead of the general library routines, which handle
-// every argument.  Each is its Taylor series after an exact reduction.
+// every argument.  Each is a short series after a reduction to a small argument.
 
-// ln u to about one ulp: u = 2^e m with m in [sqrt(1/2), sqrt(2)) (exact),
-// ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 3 - 2 sqrt(2) (m - 1 is
-// exact), atanh s = s + s^3/3 + ... + s^19/19 (the first omitted term is
-// below 2^-58 relative), and ln u = e ln2_hi + (ln m + e ln2_lo), where ln2_hi
-// is ln 2 with its last 11 mantissa bits cleared, so e ln2_hi is exact.
-__host__ __device__ __forceinline__ double log_unit(double u)
+// ln u to about one ulp, table-driven (the reduction of P. T. P. Tang, ACM
+// TOMS 16, 1990): u = 2^e m with m in [3/4, 3/2) (exact); the 7 leading
+// fraction bits of m pick the entry j of tbl (log_table.h, 128 entries, in
+// LDS in the kernels) with c_j near 1 over the bin's midpoint and t_j + tl_j
+// = -ln c_j; r = m c_j - 1 in one rounding (|r| <= 2^-7; r = m - 1 exactly
+// in the two bins next to m = 1, c_j = 1); ln(1 + r) = r - r^2/2 + ... -
+// r^8/8 (the first omitted term is below 2^-59 relative); and
+// ln u = (e ln2_hi + t_j) + (e ln2_lo + tl_j + ln(1 + r)), where ln2_hi is
+// ln 2 with its last 11 mantissa bits cleared, so e ln2_hi is exact.
+__host__ __device__ __forceinline__ double log_unit(double u, const LogEntry *tbl)
 {
     int e = 0;
     double m = frexp(u, &e);  // u = m 2^e, m in [1/2, 1)
-    if (m < 0x1.6a09e667f3bcdp-1) {  // below sqrt(1/2): m in [1, sqrt(2))
+    if (m < 0.75) {           // m in [3/4, 3/2)
         m *= 2.0;
         e -= 1;
     }
-    const double s = (m - 1.0) / (m + 1.0);
-    const double z = s * s;
-    double p = 1.0 / 19;
-    p = fma(p, z, 1.0 / 17);
-    p = fma(p, z, 1.0 / 15);
-    p = fma(p, z, 1.0 / 13);
-    p = fma(p, z, 1.0 / 11);
-    p = fma(p, z, 1.0 / 9);
-    p = fma(p, z, 1.0 / 7);
-    p = fma(p, z, 1.0 / 5);
-    p = fma(p, z, 1.0 / 3);
-    const double t = 2.0 * s;                    // exact
-    const double lm = fma(t * z, p, t);          // ln m = 2s + 2s z p(z)
+    uint64_t bits;
+    __builtin_memcpy(&bits, &m, sizeof bits);
+    const LogEntry &t = tbl[uint32_t(bits >> 45) & 127u];
+    const double r = fma(m, t.c, -1.0);
+    double p = -1.0 / 8;
+    p = fma(p, r, 1.0 / 7);
+    p = fma(p, r, -1.0 / 6);
+    p = fma(p, r, 1.0 / 5);
+    p = fma(p, r, -1.0 / 4);
+    p = fma(p, r, 1.0 / 3);
+    p = fma(p, r, -1.0 / 2);
+    const double lp = fma(r * r, p, r);  // ln(1 + r)
     constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
     const double de = double(e);
-    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    return fma(de, kLn2Hi, t.t) + (fma(de, kLn2Lo, t.tl) + lp);
 }
 
 // cos^2(2 pi u): with t = 4u = k + f (k = nearest integer, |f| <= 1/2, both

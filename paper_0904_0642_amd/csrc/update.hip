@@ -31,6 +31,16 @@ __device__ __forceinline__ bool inv_norm(double k2, double &ik)
     return true;
 }
 
+// The logarithm table of log_unit, copied into LDS by every update kernel
+// before its first draw (fill_log_table: all threads of the block).
+__shared__ LogEntry s_log_table[128];
+
+__device__ __forceinline__ void fill_log_table()
+{
+    for (uint32_t i = threadIdx.x; i < 128u; i += blockDim.x) s_log_table[i] = kLogTable[i];
+    __syncthreads();
+}
+
 // U <- R_IJ(r) U and W <- R_IJ(r) W: the 2x2 matrix r mixes rows I and J.
 template <typename H, int I, int J>
 __device__ __forceinline__ void rotate_rows(mat3<H> &U, mat3<H> &W, const cx<H> &r00, const cx<H> &r01,
@@ -83,7 +93,7 @@ __device__ __forceinline__ void su2_heatbath(mat3<H> &U, mat3<H> &W, uint32_t li
             make_uint4(lid, sweep, (uint32_t(SUB) << 16) | (uint32_t(hit) << 1), kTagUpdate), k0, k1);
         ++attempts;
         const double c2 = cos2_turn(u01(r.y));  // cos^2(2 pi u)
-        delta = -(log_unit(u01(r.x)) + c2 * log_unit(u01(r.z))) * inv_alpha;
+        delta = -(log_unit(u01(r.x), s_log_table) + c2 * log_unit(u01(r.z), s_log_table)) * inv_alpha;
         const double r4 = u01(r.w);
         if (r4 * r4 <= 1.0 - 0.5 * delta) {
             ok = true;
@@ -512,6 +522,7 @@ __device__ __forceinline__ uint32_t walk_block(const UpdateArgs &a)
 template <int D, int PREC, int WAVES, int NC = 1>
 __global__ void __launch_bounds__(256, WAVES) update_kernel(UpdateArgs a)
 {
+    fill_log_table();
     // the launch order only decides which link a thread takes; the update
     // itself is one inlined body for every order
     const uint32_t b = walk_block(a);
@@ -575,6 +586,7 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t gen)
 template <int D, int PREC, int THREADS>
 __global__ void __launch_bounds__(THREADS, persistent_waves(PREC)) update_persistent_kernel(UpdateArgs a, int n_sweeps)
 {
+    fill_log_table();
     const uint32_t sweep0 = *a.sweep;
     const uint32_t G = gridDim.x, T = a.total_blocks;
     uint32_t first = blockIdx.x, last = T, step = G;

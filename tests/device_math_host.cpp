@@ -16,7 +16,7 @@ int main()
         float sf, cf;
         su3hb::sincos_turn<double>(u, &sd, &cd);
         su3hb::sincos_turn<float>(u, &sf, &cf);
-        std::printf("%a %a %a %a %a %a\n", su3hb::log_unit(u), su3hb::cos2_turn(u), sd, cd, double(sf), double(cf));
+        std::printf("%a %a %a %a %a %a\n", su3hb::log_unit(u, su3hb::kLogTable), su3hb::cos2_turn(u), sd, cd, double(sf), double(cf));
     }
     return 0;
 }
