@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_0642_amd", "csrc", f)
-                  for f in ("update.hip", "device_math.h", "geometry.h", "layout.h")]
+                  for f in ("update.hip", "device_math.h", "geometry.h", "layout.h", "log_table.h")]
 
 WORKLOADS = {
     # name: (extents, precision, beta)
