@@ -583,18 +583,23 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> stored_form_r(const 
     return r;
 }
 
-// Rows 0 and 1 of a link as stored by 12-real storage (row 2 left unset).
+// Rows 0 and 1 of a link (row 2 left unset): the first six stored elements
+// of every storage form.
 template <int PREC>
 __device__ __forceinline__ mat3<typename Store<PREC>::real> load_rows01(const LinkRef &r)
 {
     using R = typename Store<PREC>::real;
-    static_assert(Store<PREC>::NE == 6 && sizeof(R) == 4, "rows 0 and 1 of FP32 12-real storage");
     mat3<R> m;
+    if constexpr (sizeof(R) == 8) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const nt_float4 v = read_packet<nt_float4, false>(packet_ptr<PREC>(r, j));
-        m.e[(2 * j) / 3][(2 * j) % 3] = cx<R>{v.x, v.y};
-        m.e[(2 * j + 1) / 3][(2 * j + 1) % 3] = cx<R>{v.z, v.w};
+        for (int e = 0; e < 6; ++e) m.e[e / 3][e % 3] = load_elem<PREC>(r, e);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const nt_float4 v = read_packet<nt_float4, false>(packet_ptr<PREC>(r, j));
+            m.e[(2 * j) / 3][(2 * j) % 3] = cx<R>{v.x, v.y};
+            m.e[(2 * j + 1) / 3][(2 * j + 1) % 3] = cx<R>{v.z, v.w};
+        }
     }
     return m;
 }
@@ -650,23 +655,30 @@ __device__ __forceinline__ mat3<typename Store<PREC>::real> fetch_rows01(const L
     return load_rows01<PREC>(s.ref);
 }
 
-// Both staples of one plane for FP32 12-real storage.  Every product of
-// SU(3) matrices is in SU(3), so only its rows 0 and 1 are multiplied out
-// and row 2 is conj(row0 x row1); then F3, F1 and B2 are needed only as
-// the two rows storage holds:
-//   M = F3 F2 (rows 0, 1 from F3's stored rows), Q = F1 M^dag (rows 0, 1
-//   from F1's stored rows): forward staple F1 (F3 F2)^dag = Q;
-//   N = B2 B1 (rows 0, 1 from B2's stored rows), R = N^dag B3: backward
+// Both staples of plane (mu, nu), with F1 = U_nu(x+mu), F2 = U_mu(x+nu),
+// F3 = U_nu(x), B1 = U_nu(x+mu-nu), B2 = U_mu(x-nu), B3 = U_nu(x-nu):
+// acc += wf F1 (F3 F2)^dag + wb (B2 B1)^dag B3.  Every product of SU(3)
+// matrices is in SU(3), so only its rows 0 and 1 are multiplied out and row
+// 2 is conj(row0 x row1); then F3, F1 and B2 are needed only as their rows 0
+// and 1 (6 of 9 packets in 18-real storage):
+//   M = F3 F2 (rows 0, 1 from F3's rows 0, 1), Q = F1 M^dag (rows 0, 1 from
+//   F1's rows 0, 1): the forward staple F1 (F3 F2)^dag = Q;
+//   N = B2 B1 (rows 0, 1 from B2's rows 0, 1), R = N^dag B3: the backward
 //   staple (B2 B1)^dag B3 = R;
-// acc += wf Q + wb R.  The loads keep the partner-pair order of the general
-// form below.  CLASSES as there, with Q and R as the unweighted terms.
-template <int PREC, bool CLASSES>
-__device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
-                                                     const LinkSrc<PREC> &f2, const LinkRef &f3, const LinkRef &b1,
-                                                     const LinkSrc<PREC> &b2, const LinkRef &b3,
-                                                     typename Store<PREC>::real wf, typename Store<PREC>::real wb,
-                                                     cx<typename Store<PREC>::real> *cls, uint32_t stride,
-                                                     uint32_t t, int cf, int cb)
+// acc += wf Q + wb R.  Every link a slice reads is still read whole by one of
+// its two readers (F3 of x is B1 of x - mu + nu, F1 of x is B3 of
+// x + mu + nu, F2 of x is B2 of x + 2 nu).  The loads come in partner pairs
+// (F3 with B1, F2 with B2, F1 with B3), so the second read of a line comes
+// while the first has it in L2.  CLASSES (the fused measurement on two
+// layers): the unweighted Q and R are also added to class sums cf and cb in
+// LDS (cls, element-major with the given stride, thread slot t).
+template <int PREC, bool CLASSES = false>
+__device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
+                                                  const LinkSrc<PREC> &f2, const LinkRef &f3, const LinkRef &b1,
+                                                  const LinkSrc<PREC> &b2, const LinkRef &b3,
+                                                  typename Store<PREC>::real wf, typename Store<PREC>::real wb,
+                                                  cx<typename Store<PREC>::real> *cls = nullptr,
+                                                  uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
 {
     using R = typename Store<PREC>::real;
     const mat3<R> m3 = load_rows01<PREC>(f3);
@@ -733,91 +745,6 @@ __device__ __forceinline__ void acc_plane_staples_12(mat3<typename Store<PREC>::
             cx<R> &be = cls[(cb * 9 + e) * stride + t];
             be.re += Rb.e[e / 3][e % 3].re;
             be.im += Rb.e[e / 3][e % 3].im;
-        }
-    }
-}
-
-template <int PREC, bool CLASSES = false>
-__device__ __forceinline__ void acc_plane_staples(mat3<typename Store<PREC>::real> &acc, const LinkRef &f1,
-                                                  const LinkSrc<PREC> &f2, const LinkRef &f3, const LinkRef &b1,
-                                                  const LinkSrc<PREC> &b2, const LinkRef &b3,
-                                                  typename Store<PREC>::real wf, typename Store<PREC>::real wb,
-                                                  cx<typename Store<PREC>::real> *cls = nullptr,
-                                                  uint32_t stride = 0, uint32_t t = 0, int cf = 0, int cb = 0)
-{
-    using R = typename Store<PREC>::real;
-    if constexpr (Store<PREC>::NE == 6 && sizeof(R) == 4) {
-        acc_plane_staples_12<PREC, CLASSES>(acc, f1, f2, f3, b1, b2, b3, wf, wb, cls, stride, t, cf, cb);
-        return;
-    }
-    const mat3<R> m3 = load_link<PREC>(f3);
-    const mat3<R> mb1 = load_link<PREC>(b1);
-    // T_ij = wf conj(sum_k F3_jk F2_ki): row k of F2 adds to every T_ij
-    mat3<R> T, Tu;
-    set_zero(T);
-    {
-        const mat3<R> m2 = fetch_link<PREC>(f2);
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) cfma_cn(T.e[i][j], m3.e[j][k], cx<R>{m2.e[k][i].re, -m2.e[k][i].im});
-        if constexpr (CLASSES) Tu = T;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) T.e[i][j] = cx<R>{wf * T.e[i][j].re, wf * T.e[i][j].im};
-    }
-    // S_ij = wb conj(sum_k B2_jk B1_ki): row j of B2 gives column j of S
-    mat3<R> S, Su;
-    {
-        const mat3<R> mb2 = fetch_link<PREC>(b2);
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                cx<R> s{R(0), R(0)};
-#pragma unroll
-                for (int k = 0; k < 3; ++k) cfma(s, mb2.e[j][k], mb1.e[k][i]);
-                S.e[i][j] = cx<R>{wb * s.re, -wb * s.im};
-                if constexpr (CLASSES) Su.e[i][j] = cx<R>{s.re, -s.im};
-            }
-    }
-    // acc += F1 T + S B3, row by row
-    const mat3<R> m1 = load_link<PREC>(f1);
-    const mat3<R> mb3 = load_link<PREC>(b3);
-    mat3<R> Fu, Bu;
-    if constexpr (CLASSES) {
-        set_zero(Fu);
-        set_zero(Bu);
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                cfma(acc.e[r][j], m1.e[r][k], T.e[k][j]);
-                if constexpr (CLASSES) cfma(Fu.e[r][j], m1.e[r][k], Tu.e[k][j]);
-            }
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cfma(acc.e[i][j], S.e[i][r], mb3.e[r][j]);
-                if constexpr (CLASSES) cfma(Bu.e[i][j], Su.e[i][r], mb3.e[r][j]);
-            }
-    }
-    if constexpr (CLASSES) {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) {
-            cx<R> &fe = cls[(cf * 9 + e) * stride + t];
-            fe.re += Fu.e[e / 3][e % 3].re;
-            fe.im += Fu.e[e / 3][e % 3].im;
-            cx<R> &be = cls[(cb * 9 + e) * stride + t];
-            be.re += Bu.e[e / 3][e % 3].re;
-            be.im += Bu.e[e / 3][e % 3].im;
         }
     }
 }
