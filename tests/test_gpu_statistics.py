@@ -222,14 +222,14 @@ def test_fp32_vs_fp64_same_plaquette():
     # FP32 link storage (FP64 heatbath, reunitarisation, accumulation) gives
     # the same observables as FP64 within the statistical error: total,
     # spacelike and timelike plaquette and the action beta sum_p (1/3) Re Tr
-    # U_p.  Each precision runs four independent chains (seeds 10..13; the
+    # U_p.  Each precision runs eight independent chains (seeds 10..17; the
     # same seeds for every precision, which only correlates the chains and
-    # makes the test conservative), pooled as the mean of the four chain
-    # means with the error of that mean, so that no single reference chain's
+    # makes the test conservative), pooled as the mean of the chain means
+    # with the error of that mean, so that no single reference chain's
     # fluctuation decides the comparison.
     names = ("total", "spacelike", "timelike", "action")
     cols = (0, 1, 2, 5)
-    seeds = (10, 11, 12, 13)
+    seeds = tuple(range(10, 18))
     res = {}
     for prec in (su3hb.FP64_18, su3hb.FP32_18, su3hb.FP32_12, su3hb.FP64_12):
         per = []
