@@ -614,12 +614,13 @@ struct LinkSrc {
     LinkRef ref;
     const cx<typename Store<PREC>::real> *stg;
     uint32_t slot, nslot;
+    bool rows;  // from global memory: read rows 0 and 1 and rebuild row 2 as their cross product
 };
 
 template <int PREC>
-__device__ __forceinline__ LinkSrc<PREC> from_global(const LinkRef &r)
+__device__ __forceinline__ LinkSrc<PREC> from_global(const LinkRef &r, bool rows = false)
 {
-    return LinkSrc<PREC>{r, nullptr, 0u, 0u};
+    return LinkSrc<PREC>{r, nullptr, 0u, 0u, rows};
 }
 
 template <int PREC>
@@ -641,8 +642,15 @@ template <int PREC>
 __device__ __forceinline__ mat3<typename Store<PREC>::real> fetch_link(const LinkSrc<PREC> &s)
 {
     if (staged(s)) {
+        // the same values as from global memory: row 2 rebuilt wherever the
+        // global read would rebuild it
         mat3<typename Store<PREC>::real> m = stored_from_lds(s);
-        if constexpr (Store<PREC>::NE == 6) third_row(m);
+        if (Store<PREC>::NE == 6 || s.rows) third_row(m);
+        return m;
+    }
+    if (s.rows) {
+        mat3<typename Store<PREC>::real> m = load_rows01<PREC>(s.ref);
+        third_row(m);
         return m;
     }
     return load_link<PREC>(s.ref);

@@ -235,8 +235,13 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
         const uint32_t tags_f = layer + l_pm + l_pn + layer;
         const uint32_t tags_b = l_mn + l_pmmn + layer + l_mn;
         // U_mu(x + nu) and U_mu(x - nu): from the wave's staging area for
-        // nu = 0, 1 when the launch stages (single-layer lattices only)
-        LinkSrc<PREC> f2 = from_global<PREC>(link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn));
+        // nu = 0, 1 when the launch stages (single-layer lattices only).
+        // A parity-q U_mu link is read by six threads (F2 of x - nu, B2 of
+        // x + nu); one whole read suffices: the first plane other than mu
+        // (nu = 0, or 1 when mu = 0) reads F2 whole, the others read rows 0
+        // and 1 like B2.
+        const bool f2_rows = nu >= 2 || (nu == 1 && mu != 0);
+        LinkSrc<PREC> f2 = from_global<PREC>(link_ref<D, PREC>(a.links, rep, l_pn, mu, q, s_pn), f2_rows);
         LinkSrc<PREC> b2 = from_global<PREC>(link_ref<D, PREC>(a.links, rep, l_mn, mu, q, s_mn));
         if (nu < 2 && stg != nullptr) {
             const uint32_t nslot = 64u + 2u * a.stage_r;
