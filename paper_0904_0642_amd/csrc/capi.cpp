@@ -1034,37 +1034,64 @@ int su3hb_autotune(su3hb_lattice *L, int budget_ms)
     const bool graph = L->use_graph;
     L->use_graph = false;
     int rc = SU3HB_OK;
+    // time candidate i: its launch, a warm-up sweep, then timed batches of
+    // at least min_reps sweeps, doubling until a batch takes target_ms (at
+    // most 64 sweeps); ms per sweep, or a negative value for a shape whose
+    // LDS does not fit (not a candidate)
+    auto time_cand = [&](size_t i, int min_reps, double target_ms, float *out) -> int {
+        int r = apply_launch(L, cands[i].block, cands[i].order, cands[i].waves);
+        if (r == SU3HB_EUNSUPPORTED) {
+            *out = -1.f;
+            return SU3HB_OK;
+        }
+        if (r) return r;
+        if (meas && (r = ensure_meas(L)) != SU3HB_OK) return r;
+        if (hipSuccess != launch_counter_set(L->stream, L->d_cursor, 0)) return fail(SU3HB_EHIP, "cursor");
+        if ((r = enqueue_sweep(L, L->stream, b, b, 8, meas)) != SU3HB_OK) return r;  // warm-up
+        int reps = min_reps;
+        float ms = 0.f;
+        for (;;) {
+            if (hipSuccess != launch_counter_set(L->stream, L->d_cursor, 0)) return fail(SU3HB_EHIP, "cursor");
+            if (hipEventRecord(e0, L->stream) != hipSuccess) return fail(SU3HB_EHIP, "event");
+            for (int k = 0; k < reps; ++k)
+                if ((r = enqueue_sweep(L, L->stream, b, b, 8, meas)) != SU3HB_OK) return r;
+            if (hipEventRecord(e1, L->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(SU3HB_EHIP, "event");
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms >= target_ms || reps >= 64) break;
+            reps *= 2;
+        }
+        *out = ms / float(reps);
+        return SU3HB_OK;
+    };
+    // two passes over every candidate with about a quarter of the budget each
     for (int pass = 0; pass < 2 && !rc; ++pass)
         for (size_t i = 0; i < cands.size() && !rc; ++i) {
-            rc = apply_launch(L, cands[i].block, cands[i].order, cands[i].waves);
-            if (rc == SU3HB_EUNSUPPORTED) {  // its LDS does not fit: not a candidate
-                rc = SU3HB_OK;
-                continue;
-            }
-            if (rc) break;
-            if (meas && (rc = ensure_meas(L)) != SU3HB_OK) break;
-            if (hipSuccess != launch_counter_set(L->stream, L->d_cursor, 0)) { rc = fail(SU3HB_EHIP, "cursor"); break; }
-            rc = enqueue_sweep(L, L->stream, b, b, 8, meas);  // warm-up
-            if (rc) break;
-            int reps = 1;
-            float ms = 0.f;
-            for (;;) {
-                if (hipSuccess != launch_counter_set(L->stream, L->d_cursor, 0)) { rc = fail(SU3HB_EHIP, "cursor"); break; }
-                if (hipEventRecord(e0, L->stream) != hipSuccess) { rc = fail(SU3HB_EHIP, "event"); break; }
-                for (int k = 0; k < reps && !rc; ++k) rc = enqueue_sweep(L, L->stream, b, b, 8, meas);
-                if (rc) break;
-                if (hipEventRecord(e1, L->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(SU3HB_EHIP, "event");
-                    break;
-                }
-                hipEventElapsedTime(&ms, e0, e1);
-                if (ms * double(cands.size()) * 4 >= budget_ms || reps >= 64) break;
-                reps *= 2;
-            }
-            if (rc) break;
-            per[i] = std::min(per[i], ms / reps);
-            if (per[i] < per[best_i]) best_i = i;
+            float t = 0.f;
+            rc = time_cand(i, 1, double(budget_ms) / (4.0 * double(cands.size())), &t);
+            if (!rc && t >= 0.f) per[i] = std::min(per[i], t);
         }
+    // the six fastest again, in three interleaved rounds of at least two
+    // sweeps each, with the other half of the budget: single sweeps of
+    // shapes within a per cent of each other do not order them reliably
+    std::vector<size_t> rank(cands.size());
+    for (size_t i = 0; i < rank.size(); ++i) rank[i] = i;
+    const size_t K = std::min<size_t>(6, rank.size());
+    std::partial_sort(rank.begin(), rank.begin() + K, rank.end(), [&](size_t x, size_t y) { return per[x] < per[y]; });
+    std::vector<float> fin(K, 1e30f);
+    for (int round = 0; round < 3 && !rc; ++round)
+        for (size_t k = 0; k < K && !rc; ++k) {
+            if (per[rank[k]] >= 1e30f) continue;
+            float t = 0.f;
+            rc = time_cand(rank[k], 2, double(budget_ms) / (6.0 * double(K)), &t);
+            if (!rc && t >= 0.f) fin[k] = std::min(fin[k], t);
+        }
+    {
+        size_t bk = 0;
+        for (size_t k = 1; k < K; ++k)
+            if (fin[k] < fin[bk]) bk = k;
+        best_i = rank[bk];
+    }
     L->use_graph = graph;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
