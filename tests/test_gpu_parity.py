@@ -438,6 +438,18 @@ def test_staged_neighbours_bit_identical(prec, ext):
     assert staged >= 6
 
 
+def test_staging_beyond_lds_is_refused():
+    # a 4096 x 4 torus stages 64 + 4096 links per wave: far beyond the LDS of
+    # a block, so the shape is refused and the launch stays as it was
+    g = su3hb.Lattice([4096, 4], seed=3, precision=su3hb.FP64_18)
+    g.set_launch(128, 1, 2)
+    with pytest.raises(su3hb.SU3HBError) as ei:
+        g.set_launch(128, 17, 2)
+    assert ei.value.code == su3hb.EUNSUPPORTED and "LDS" in str(ei.value)
+    assert g.get_launch() == (128, 1, 2)
+    g.sweep(6.0, n_hit=8, n_sweeps=1)  # still usable
+
+
 def test_graph_replay_equals_direct_launches():
     # graph replays (su3hb_sweep) against kernel-by-kernel launches
     # (su3hb_sweep_timed), with eager work and synchronisation in between
