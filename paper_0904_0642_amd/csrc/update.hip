@@ -612,8 +612,14 @@ __global__ void __launch_bounds__(THREADS, persistent_waves(PREC)) update_persis
                 // are flushed once per slice, next to the barrier's own sync
                 int att[3] = {0, 0, 0}, acc[3] = {0, 0, 0}, upd = 0;
                 double dtrace = 0.0, plaq[1] = {0.0};
-                for (uint32_t lb = first; lb < last; lb += step)
+                // alternate slices walk the block's share backwards, so a
+                // slice starts on the links its predecessor read last
+                const uint32_t n = first < last ? (last - first + step - 1) / step : 0u;
+                const bool back = ((p * D + mu) & 1) != 0;
+                for (uint32_t j = 0; j < n; ++j) {
+                    const uint32_t lb = first + (back ? n - 1u - j : j) * step;
                     block_links<D, PREC, 1>(b, lb, sweep0 + uint32_t(sw), att, acc, upd, dtrace, plaq);
+                }
                 flush_stats<1>(b, blockIdx.x, att, acc, upd, dtrace, plaq);
                 if (!grid_barrier(a.barrier, gen++)) return;
             }
