@@ -52,14 +52,22 @@ struct RepDesc {
 // Persistent batch launches: blocks of kPersistentThreads, as many per CU as
 // the kernel's registers allow (2 waves per SIMD for FP64 links, 3 for
 // FP32), slices separated by a grid barrier on a small array of counters
-// (kBarrierWords words: kBarrierLeaves leaf counters on their own 128-byte
-// lines, the top counter, an abort flag).
+// (kBarrierWords words, each counter on its own 128-byte line): the start
+// barrier's kBarrierLeaves leaf counters and top counter, an abort flag, and
+// for the slice barriers per-XCD member counts, arrival counters and go
+// words, a top counter of the XCDs and a release word.
 constexpr int kPersistentThreads = 256;
 inline constexpr int persistent_waves(int prec) { return (prec == kFP32_18 || prec == kFP32_12) ? 3 : 2; }
-constexpr int kBarrierWords = 2048;
+constexpr int kBarrierWords = 4096;
 constexpr uint32_t kBarrierLeaves = 16;
 constexpr uint32_t kBarrierTop = 1024;
 constexpr uint32_t kBarrierFlag = 1536;
+constexpr uint32_t kBarrierXcds = 16;            // XCC ids are 4 bits
+constexpr uint32_t kBarrierXcdMembers = 2048;    // + 32 x: blocks on XCD x
+constexpr uint32_t kBarrierXcdArrive = 2560;     // + 32 x
+constexpr uint32_t kBarrierXcdGo = 3072;         // + 32 x
+constexpr uint32_t kBarrierXcdTop = 3584;
+constexpr uint32_t kBarrierXcdRelease = 3712;
 constexpr uint32_t kBarrierSpinLimit = 1u << 22;
 
 // Statistics slot, padded to its own 128-byte line.

@@ -580,6 +580,72 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t gen)
     return s_ok != 0;
 }
 
+// XCD of the calling wave (hardware register XCC_ID, 4 bits).
+__device__ __forceinline__ uint32_t xcc_id()
+{
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kBarrierXcds - 1u);
+}
+
+// Wait until *w reaches target (agent-scope loads); false when the abort
+// flag is seen (checked every 64 polls) or the spin limit is passed, after
+// raising the flag so that every block leaves the kernel.
+__device__ __forceinline__ bool wait_word(uint32_t *bar, const uint32_t *w, uint32_t target)
+{
+    uint32_t spins = 0;
+    while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        ++spins;
+        if (spins > kBarrierSpinLimit ||
+            ((spins & 63u) == 0u &&
+             __hip_atomic_load(bar + kBarrierFlag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+            atomicOr(bar + kBarrierFlag, 1u);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Slice barrier of a persistent launch, with one L2 writeback and one L2
+// invalidation per XCD instead of one per block.  The XCD's L2 is shared by
+// all its blocks but not kept coherent with the other XCDs, so a block's
+// stores reach the other XCDs only through a writeback of its XCD's L2, and
+// a block sees the other XCDs' stores only after its XCD's L2 has dropped
+// its stale lines.  Every wave first waits for its own stores to complete
+// into L2; each block then arrives on its XCD's counter; the last arrival
+// of an XCD (members: blocks on that XCD, counted at the start) writes the
+// L2 back (agent release), arrives on the XCD top counter and waits for the
+// release word, which the last XCD sets; it then invalidates the L2 (agent
+// acquire) and sets its XCD's go word, on which the other blocks of the XCD
+// wait before they drop their compute unit's L1 lines.
+__device__ __forceinline__ bool xcd_barrier(uint32_t *bar, uint32_t gen, uint32_t x, uint32_t members,
+                                            uint32_t nxcd)
+{
+    __shared__ int s_ok;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok;
+        const uint32_t old =
+            __hip_atomic_fetch_add(bar + kBarrierXcdArrive + 32u * x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == (gen + 1u) * members) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t t =
+                __hip_atomic_fetch_add(bar + kBarrierXcdTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t + 1u == (gen + 1u) * nxcd)
+                __hip_atomic_store(bar + kBarrierXcdRelease, gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = wait_word(bar, bar + kBarrierXcdRelease, gen + 1u);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(bar + kBarrierXcdGo + 32u * x, gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = wait_word(bar, bar + kBarrierXcdGo + 32u * x, gen + 1u);
+            asm volatile("buffer_inv sc0" ::: "memory");
+        }
+        s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
 // Persistent form for batches: every resident block (as many per CU as fit)
 // stays for n_sweeps sweeps, loops over the logical blocks of every slice and meets the others
 // at a grid barrier between slices (the next slice reads links this one
@@ -592,6 +658,25 @@ template <int D, int PREC, int THREADS>
 __global__ void __launch_bounds__(THREADS, persistent_waves(PREC)) update_persistent_kernel(UpdateArgs a, int n_sweeps)
 {
     fill_log_table();
+    // count the blocks of every XCD, then one grid-wide barrier (per-block
+    // cache maintenance) before the counts are read
+    __shared__ uint32_t s_members, s_nxcd;
+    const uint32_t x = xcc_id();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(a.barrier + kBarrierXcdMembers + 32u * x, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_barrier(a.barrier, 0)) return;
+    if (threadIdx.x == 0) {
+        uint32_t n = 0;
+        for (uint32_t k = 0; k < kBarrierXcds; ++k)
+            n += __hip_atomic_load(a.barrier + kBarrierXcdMembers + 32u * k, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) != 0u ? 1u : 0u;
+        s_members = __hip_atomic_load(a.barrier + kBarrierXcdMembers + 32u * x, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+        s_nxcd = n;
+    }
+    __syncthreads();
+    const uint32_t members = s_members, nxcd = s_nxcd;
     const uint32_t sweep0 = *a.sweep;
     const uint32_t G = gridDim.x, T = a.total_blocks;
     uint32_t first = blockIdx.x, last = T, step = G;
@@ -621,7 +706,7 @@ __global__ void __launch_bounds__(THREADS, persistent_waves(PREC)) update_persis
                     block_links<D, PREC, 1>(b, lb, sweep0 + uint32_t(sw), att, acc, upd, dtrace, plaq);
                 }
                 flush_stats<1>(b, blockIdx.x, att, acc, upd, dtrace, plaq);
-                if (!grid_barrier(a.barrier, gen++)) return;
+                if (!xcd_barrier(a.barrier, gen++, x, members, nxcd)) return;
             }
         }
     }
