@@ -14,6 +14,9 @@ sweeps; `roofline` prices the slice-update kernel against 8 TB/s with the
 algorithmic bytes per launch (2D+1) * bytes_per_link * V/2 (one read of every
 link of the lattice, one write of the updated half-direction), divided by the
 kernel's average duration measured with HIP events around each launch.
+`roofline.traffic` is the memory-side bytes per launch that rocprofv3
+counter runs (FETCH_SIZE, WRITE_SIZE, scaled by a copy of known size)
+recorded for this kernel source in the launch shape in effect, else null.
 """
 from __future__ import annotations
 
@@ -55,16 +58,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, algorithmic_bytes: float):
-    """HBM bytes per update launch from the committed rocprofv3 counter runs,
-    or None when absent or taken on different kernel sources."""
+def measured_traffic(workload: str, launch) -> int | None:
+    """Memory-side bytes per update launch from the committed rocprofv3
+    counter runs of this workload in this launch shape (block, order, waves
+    as the library reports them); None when no run covers the shape or the
+    runs were taken on different kernel sources."""
     path = os.path.join(PROFILES, f"update_kernel_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    entry = rec.get("by_launch", {}).get("%d,%d,%d" % tuple(launch))
+    return None if entry is None else entry.get("hbm_bytes_per_launch")
 
 
 def parse_launch(text: str):
@@ -103,7 +109,7 @@ def run_leg(name: str, steps: int, warmup: int, n_hit: int, autotune_ms: int, la
     S = BYTES_PER_LINK[prec]
     bytes_per_launch = (2 * D + 1) * S * (V // 2)
     achieved = bytes_per_launch / (upd_ms * 1e-3) / 1e9
-    traffic = measured_traffic(name, bytes_per_launch)
+    traffic = measured_traffic(name, (block, order, waves))
     plaq = series[:, 0]
     out = {
         "rate": rate, "secs": secs, "ms_per_step": 1e3 * secs / steps,
@@ -354,7 +360,7 @@ def main():
     ap.add_argument("--workload", default="48^4-fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--compare", default="64^4-fp32-12", help="second leg ('' to skip)")
     ap.add_argument("--n-hit", type=int, default=8)
-    ap.add_argument("--autotune-ms", type=int, default=400)
+    ap.add_argument("--autotune-ms", type=int, default=1600)
     ap.add_argument("--launch", default="", help="block,order,waves for the main leg instead of autotuning")
     ap.add_argument("--compare-launch", default="", help="block,order,waves for the comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
