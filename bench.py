@@ -46,6 +46,15 @@ WORKLOADS = {
     "16^4-fp64": ((16, 16, 16, 16), 0, 6.0),
 }
 PREC_NAME = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12", 3: "fp64-12"}
+# the paper's small runs (Sec. 3, Tables 1-3 and the D = 2 check), FP64 links:
+# name: (extents, layers, glued directions, cold start, beta, sweeps)
+SMALL_CONFIGS = {
+    "config1_4^4_cold": ((4, 4, 4, 4), 1, 0, True, 6.0, 20),
+    "config2a_16^4_hot_beta5.7": ((16, 16, 16, 16), 1, 0, False, 5.7, 200),
+    "config2a_16^4_hot_beta6.0": ((16, 16, 16, 16), 1, 0, False, 6.0, 200),
+    "config2b_32^2_hot": ((32, 32), 1, 0, False, 4.0, 20000),
+    "config3_2x24^3x8_hot": ((24, 24, 24, 8), 2, 0xF, False, 5.69, 500),
+}
 PREC_DTYPE = {0: "f64", 1: "f32 links + f64 heatbath", 2: "f32 (12-real) links + f64 heatbath",
               3: "f64 (12-real links)"}
 BYTES_PER_LINK = {0: 144, 1: 72, 2: 48, 3: 96}
@@ -311,6 +320,65 @@ def precision_study(n_hit: int, ntherm: int = 200, nmeas: int = 2000):
     return res
 
 
+def small_configs_leg(n_hit: int):
+    """The paper's small runs at their full sweep counts on the GPU (FP64-18,
+    plaquettes after every sweep, seed 1, the library's default launch).
+    These lattices sit in the Infinity Cache, so only the rate is given."""
+    import torch
+
+    import paper_0904_0642_amd as su3hb
+
+    out = {}
+    for name, (ext, nlat, mask, cold, beta, sweeps) in SMALL_CONFIGS.items():
+        lat = su3hb.Lattice(ext, nlat=nlat, dlt_mask=mask, precision=su3hb.FP64_18,
+                            start=su3hb.COLD if cold else su3hb.HOT, seed=1)
+        links = nlat * int(np.prod(ext)) * len(ext)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = lat.sweep_measure(beta, n_hit=n_hit, n_sweeps=sweeps)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out[name] = {"value": round(sweeps * links / secs, 1), "unit": "link updates/s", "sweeps": sweeps,
+                     "seconds": round(secs, 4), "beta": beta, "plaquette_last": float(ser[-1, 0])}
+        lat.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def oracle_small_configs(n_hit: int, threads: int):
+    """The FP64 oracle on the same small runs, a sweep and a plaquette
+    measurement at a time: config 1 in full, the others on a bounded sample
+    of their sweeps (at least one, until about 2 s have passed), on all host
+    threads and on one."""
+    import oracle
+
+    out = {}
+    for name, (ext, nlat, mask, cold, beta, sweeps) in SMALL_CONFIGS.items():
+        links = nlat * int(np.prod(ext)) * len(ext)
+        res = {"unit": "link updates/s", "sweeps_in_full_run": sweeps}
+        for label, th, budget in (("all_threads", threads, 2.0), ("single_thread", 1, 2.0)):
+            o = oracle.Lattice(list(ext), nlat=nlat, dlt_mask=mask, seed=1, threads=th)
+            if cold:
+                o.cold_start()
+            else:
+                o.hot_start()
+            done_sweeps, t0 = 0, time.perf_counter()
+            while done_sweeps < sweeps:
+                o.sweep(beta, nhit=n_hit)
+                o.plaquette(beta)
+                done_sweeps += 1
+                if time.perf_counter() - t0 >= budget:
+                    break
+            secs = time.perf_counter() - t0
+            rate = done_sweeps * links / secs
+            res[label] = {"value": round(rate, 1), "cores": th, "sweeps_timed": done_sweeps,
+                          "seconds": round(secs, 3),
+                          "full_run_seconds": round(sweeps * links / rate, 2)}
+            del o
+        out[name] = res
+    return out
+
+
 def oracle_rate(name: str, n_hit: int, threads: int, min_secs: float, max_sweeps: int):
     """Link updates per second of the FP64 oracle on checkerboard slices of
     the hot-started lattice in sweep order (parity 0, 1; directions
@@ -338,7 +406,8 @@ def oracle_rate(name: str, n_hit: int, threads: int, min_secs: float, max_sweeps
 
 def cpu_baseline(name: str, n_hit: int, min_secs: float = 10.0, max_sweeps: int = 6):
     """The FP64 oracle on a bounded sample of the same workload, on all host
-    threads the run may use and on one thread."""
+    threads the run may use and on one thread, and on the paper's small runs
+    (oracle_small_configs)."""
     ext, prec, beta = WORKLOADS[name]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rate, slices, n, secs = oracle_rate(name, n_hit, threads, min_secs, max_sweeps)
@@ -349,7 +418,8 @@ def cpu_baseline(name: str, n_hit: int, min_secs: float = 10.0, max_sweeps: int 
                       f"{'x'.join(map(str, ext))} lattice at beta={beta}, n_hit={n_hit}, FP64 C oracle, "
                       f"OpenMP {threads} threads, {secs:.2f} s",
             "single_thread": {"value": rate1, "unit": "link updates/s", "cores": 1,
-                              "sample": f"{slices1} slices ({n1} link updates), 1 thread, {secs1:.2f} s"}}
+                              "sample": f"{slices1} slices ({n1} link updates), 1 thread, {secs1:.2f} s"},
+            "small_configs": oracle_small_configs(n_hit, threads)}
 
 
 def main():
@@ -458,6 +528,8 @@ def main():
                 "update_kernel_ms": round(leg["update_kernel_ms"], 5), "launch": leg["launch"],
                 "rate_ratio_vs_main": round(leg["rate"] / main_leg["rate"], 3),
             }
+        line["small_configs"] = small_configs_leg(args.n_hit)
+        done("small configs")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.n_hit)
         done("cpu baseline")
