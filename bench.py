@@ -48,6 +48,7 @@ WORKLOADS = {
 PREC_NAME = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12", 3: "fp64-12"}
 # the paper's small runs (Sec. 3, Tables 1-3 and the D = 2 check), FP64 links:
 # name: (extents, layers, glued directions, cold start, beta, sweeps)
+EXTRA_LEGS = ("batch", "dlt", "precision", "overrelax", "full_size", "small_configs")
 SMALL_CONFIGS = {
     "config1_4^4_cold": ((4, 4, 4, 4), 1, 0, True, 6.0, 20),
     "config2a_16^4_hot_beta5.7": ((16, 16, 16, 16), 1, 0, False, 5.7, 200),
@@ -175,7 +176,8 @@ def overrelax_leg(name: str, steps: int, warmup: int, autotune_ms: int):
     return out
 
 
-def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int = 128):
+def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int = 128, launch=None,
+              modes=("graph_per_slice", "persistent")):
     """Independent replicas of mixed sizes (8^4, 12^4, 16^3x4 round robin),
     beta uniform in [5.5, 6.5], FP32 links, one launch per slice for all
     replicas replayed from a HIP graph, and the same sweeps as one persistent
@@ -189,8 +191,11 @@ def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int =
     reps = [(e, b, sd, st) for e, b, sd, st in zip(t.extents, t.betas, t.seeds, t.starts)]
     prec = su3hb.FP32_18
     b = su3hb.Batch(4, reps, precision=prec)
-    if autotune_ms > 0:
+    if launch is not None:
+        b.set_launch(*launch)
+    elif autotune_ms > 0:
         b.autotune(autotune_ms)
+    shape = su3hb.su3hb_get_launch(b._h)
     if warmup > 0:
         b.sweep(n_hit=n_hit, n_sweeps=warmup, mode=0)
     links = t.links_per_sweep
@@ -198,6 +203,8 @@ def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int =
     upd_ms = timing[0] / max(timing[1], 1)
     out = {}
     for mode, label in ((0, "graph_per_slice"), (1, "persistent")):
+        if label not in modes:
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.sweep(n_hit=n_hit, n_sweeps=steps, mode=mode)
@@ -212,9 +219,11 @@ def batch_leg(steps: int, warmup: int, n_hit: int, autotune_ms: int, nrep: int =
            "replicas": nrep, "links_per_sweep": links, "precision": PREC_NAME[prec],
            "update_kernel_ms": round(upd_ms, 5),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": bytes_per_launch},
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(f"batch-{nrep}-{PREC_NAME[prec]}", shape),
+                        "algorithmic_bytes_per_launch": bytes_per_launch},
            "plaquette_mean_over_replicas": float(np.mean(plaq)),
-           "launch": dict(zip(("block", "order", "waves"), su3hb.su3hb_get_launch(b._h)))}
+           "launch": dict(zip(("block", "order", "waves"), shape))}
     b.close()
     torch.cuda.empty_cache()
     return res
@@ -435,6 +444,11 @@ def main():
     ap.add_argument("--compare-launch", default="", help="block,order,waves for the comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true", help="skip the batch, DLT and precision legs")
+    ap.add_argument("--extra-legs", default=",".join(EXTRA_LEGS),
+                    help="comma-separated subset of the extra legs to run: " + ", ".join(EXTRA_LEGS))
+    ap.add_argument("--batch-launch", default="", help="block,order,waves for the batch leg instead of autotuning")
+    ap.add_argument("--batch-modes", default="graph_per_slice,persistent",
+                    help="batch modes to time: graph_per_slice, persistent (cooperative launch)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()
@@ -507,16 +521,27 @@ def main():
             "plaquette_first_last": leg["plaquette_first_last"],
             "rate_ratio_vs_main": round(leg["rate"] / main_leg["rate"], 3),
         }
-    if not args.no_extra_legs:
-        line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms)
+    extra = set() if args.no_extra_legs else {x for x in args.extra_legs.split(",") if x}
+    unknown = extra - set(EXTRA_LEGS)
+    if unknown:
+        print(f"unknown extra legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    if "batch" in extra:
+        line["batch_128_replicas"] = batch_leg(args.steps, args.warmup, args.n_hit, args.autotune_ms,
+                                               launch=parse_launch(args.batch_launch),
+                                               modes=tuple(args.batch_modes.split(",")))
         done("batch")
+    if "dlt" in extra:
         line["dlt_2x24^3x8"] = dlt_leg(args.n_hit, args.autotune_ms)
         done("double-layered torus")
+    if "precision" in extra:
         line["precision_study"] = precision_study(args.n_hit)
         done("precision study")
+    if "overrelax" in extra:
         line["overrelaxation_" + args.workload] = overrelax_leg(args.workload, args.steps, args.warmup,
                                                                 args.autotune_ms)
         done("overrelaxation")
+    if "full_size" in extra:
         for name in ("64^4-fp32-18", "48^4-fp64-12"):
             if name in (args.workload, args.compare):
                 continue
@@ -528,6 +553,7 @@ def main():
                 "update_kernel_ms": round(leg["update_kernel_ms"], 5), "launch": leg["launch"],
                 "rate_ratio_vs_main": round(leg["rate"] / main_leg["rate"], 3),
             }
+    if "small_configs" in extra:
         line["small_configs"] = small_configs_leg(args.n_hit)
         done("small configs")
     if not args.no_cpu_baseline:
