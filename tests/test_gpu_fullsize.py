@@ -104,6 +104,15 @@ def test_64x64x64x64_fp32_12(oracle_mod):
     sampled_sweep_parity(oracle_mod, ext, su3hb.FP32_12, 6.2, ALL_SLICES, 1e-4)
 
 
+@pytest.mark.timeout(600)
+def test_64x64x64x64_fp32_18_past_4gb(oracle_mod):
+    # 4.83 GB of links: the slab of U_3 on odd sites starts 4.23 GB into the
+    # buffer, so slice (1, 3) updates links whose byte offsets need more than
+    # 32 bits, and slice (0, 3) reads them as its U_mu neighbours
+    ext = (64, 64, 64, 64)
+    sampled_sweep_parity(oracle_mod, ext, su3hb.FP32_18, 6.2, {(0, 3), (1, 3)}, 1e-4)
+
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("prec,tol", [(su3hb.FP64_18, 1e-10), (su3hb.FP32_18, 1e-4), (su3hb.FP32_12, 1e-4)])
 def test_double_layered_2x24x24x24x8(oracle_mod, prec, tol):
