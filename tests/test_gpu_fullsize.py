@@ -104,6 +104,14 @@ def test_64x64x64x64_fp32_12(oracle_mod):
     sampled_sweep_parity(oracle_mod, ext, su3hb.FP32_12, 6.2, ALL_SLICES, 1e-4)
 
 
+@pytest.mark.timeout(300)
+def test_48x48x48x48_fp64_12(oracle_mod):
+    # the benchmark's full-size FP64-12 leg: two stored rows, row 2 rebuilt
+    # on every load, against the oracle's full matrices
+    ext = (48, 48, 48, 48)
+    sampled_sweep_parity(oracle_mod, ext, su3hb.FP64_12, 6.2, ALL_SLICES, 1e-10)
+
+
 @pytest.mark.timeout(600)
 def test_64x64x64x64_fp32_18_past_4gb(oracle_mod):
     # 4.83 GB of links: the slab of U_3 on odd sites starts 4.23 GB into the
