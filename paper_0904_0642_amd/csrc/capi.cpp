@@ -180,6 +180,7 @@ RepDesc make_rep(int nd, const int *ext, int nlat, unsigned glued, int lat2test,
         r.stride[i] = st;
         st *= uint32_t(ext[i]);
     }
+    for (int i = 0; i + 1 < nd; ++i) r.div[i] = div_magic(i == 0 ? uint32_t(ext[0]) / 2u : uint32_t(ext[i]));
     r.V = st;
     r.Vh = st / 2;
     r.Vhp = padded_half(r.Vh);

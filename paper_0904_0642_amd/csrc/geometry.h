@@ -29,6 +29,12 @@ __device__ __forceinline__ int find_replica(const RepDesc *__restrict__ reps, in
     return lo;
 }
 
+// x / d for x < 2^31 by the multiplier of d (div_magic).
+__device__ __forceinline__ uint32_t div_by(uint32_t x, DivMagic dm)
+{
+    return uint32_t((uint64_t(x) * dm.m) >> dm.s);
+}
+
 // A site of parity p given by its half index h (site number s = 2h + b).
 // Eq. (i_s) with direction 0 fastest: since n0 is even, sites 2h and 2h+1
 // share x1..x_{D-1} and have opposite parity, so h indexes each checkerboard.
@@ -38,16 +44,21 @@ struct Site {
     uint32_t s;
     uint32_t layer;
 
+    // MAGIC: the divisions by the extents use the replica's multipliers (a
+    // 64-bit product and a shift each instead of the compiler's expansion of
+    // a division by a run-time value, about 16 vector instructions); exact
+    // because h < 2^31.
+    template <bool MAGIC = false>
     __device__ __forceinline__ void from_half(const RepDesc &rep, uint32_t h, int p, uint32_t lay)
     {
         const uint32_t nh0 = uint32_t(rep.n[0]) >> 1;
-        uint32_t rest = h / nh0;
+        uint32_t rest = MAGIC ? div_by(h, rep.div[0]) : h / nh0;
         const uint32_t hx = h - rest * nh0;
         int psum = p;
 #pragma unroll
         for (int i = 1; i < D; ++i) {
             if (i < D - 1) {
-                const uint32_t q = rest / uint32_t(rep.n[i]);
+                const uint32_t q = MAGIC ? div_by(rest, rep.div[i]) : rest / uint32_t(rep.n[i]);
                 x[i] = int(rest - q * uint32_t(rep.n[i]));
                 rest = q;
             } else {

@@ -25,6 +25,22 @@ inline constexpr int bytes_per_link(int prec) { return elems_per_link(prec) * by
 constexpr uint32_t kTile = 64;
 inline constexpr uint32_t padded_half(uint32_t Vh) { return (Vh + kTile - 1) / kTile * kTile; }
 
+// Division by an invariant integer (T. Granlund and P. L. Montgomery, PLDI
+// 1994): for d >= 1 and 0 <= x < 2^31, x / d = (x m) >> s with
+// l = ceil(log2 d), s = 31 + l and m = ceil(2^s / d), which is below 2^32
+// (so m d - 2^s < d <= 2^l, the condition of their Theorem 4.2).
+struct DivMagic {
+    uint32_t m, s;
+};
+
+inline DivMagic div_magic(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    const uint32_t s = 31u + l;
+    return DivMagic{uint32_t(((uint64_t(1) << s) + d - 1u) / d), s};
+}
+
 // One lattice ("replica").  A single lattice is a batch of one.  Its links
 // start `elem_offset` complex elements into the batch's link buffer and are
 // laid out as [layer][mu][parity][tile][packet][kTile].
@@ -47,6 +63,7 @@ struct RepDesc {
     uint32_t plq_spt;        // plaquettes per thread in the plaquette launch
     uint32_t pers_block0;    // first block in a persistent launch (kPersistentThreads links per block)
     uint32_t pers_blocks;
+    DivMagic div[kMaxD - 1];  // division by n0 / 2 (entry 0) and by n_i (entry i, 0 < i < D - 1)
 };
 
 // Persistent batch launches: blocks of kPersistentThreads, as many per CU as

@@ -190,7 +190,11 @@ __device__ __forceinline__ void update_link(const UpdateArgs &a, const RepDesc &
         h -= Vh;
     }
     Site<D> x;
-    x.from_half(rep, h, p, layer);
+    // FP32-12 on single-layer lattices, the kernel bound by its vector ALU
+    // work, takes the multipliers; the others keep the division, which holds
+    // their register counts (FP32-18 and the two-layer FP32-12 measurement
+    // sit at the 128 registers of 4 waves per SIMD)
+    x.template from_half<PREC == kFP32_12 && NC == 1>(rep, h, p, layer);
     const bool single = rep.nlat == 1;
     const uint32_t glued = single ? 0u : rep.glued;
     const double beta0 = a.use_rep_beta ? rep.beta0 : a.beta0;
